@@ -1,0 +1,88 @@
+"""ctypes binding of libdaba.so (include/daba.h).
+
+Argument marshalling only: every step of the iteration runs in the library's
+gfx950 kernels.  PyTorch supplies the device workspace and the stream.  If
+the library has not been built this module raises on import; there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdaba.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "daba.h")
+
+DABA_OK = 0
+ERRORS = {-1: "DABA_E_INVAL", -2: "DABA_E_NOMEM", -3: "DABA_E_HIP", -4: "DABA_E_NONFINITE", -5: "DABA_E_DEGENERATE"}
+LOSS = {"trivial": 0, "huber": 1, "welsch": 2}
+PRECISION = {"fp64": 0, "fp32_mixed": 1}
+NEVER_RESTART = 1
+ALWAYS_RESTART = 2
+MAX_PARTITIONS = 64
+
+_P = C.POINTER
+
+
+class DabaProblem(C.Structure):
+    _fields_ = [("n_cameras", C.c_int64), ("n_landmarks", C.c_int64), ("n_obs", C.c_int64),
+                ("obs_camera", _P(C.c_int32)), ("obs_landmark", _P(C.c_int32)), ("obs_uv", _P(C.c_double)),
+                ("cameras", _P(C.c_double)), ("landmarks", _P(C.c_double)),
+                ("n_partitions", C.c_int32), ("camera_partition", _P(C.c_int32)),
+                ("landmark_partition", _P(C.c_int32)), ("unit_scale", C.c_double)]
+
+
+class DabaOptions(C.Structure):
+    _fields_ = [("loss", C.c_int32), ("loss_delta", C.c_double), ("xi", C.c_double), ("eta", C.c_double),
+                ("accelerate", C.c_int32), ("inner_steps", C.c_int32), ("precision", C.c_int32),
+                ("debug_flags", C.c_uint64)]
+
+
+class DabaError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {detail}")
+        self.code = code
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions include/daba.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(daba_[a-z_]+)\s*\(", text)))
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_2305_07026_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, d, i = C.c_void_p, C.c_double, C.c_int
+    pd = _P(d)
+    lib.daba_workspace_bytes.argtypes = [_P(DabaProblem), _P(DabaOptions)]
+    lib.daba_workspace_bytes.restype = C.c_size_t
+    lib.daba_create.argtypes = [_P(DabaProblem), _P(DabaOptions), vp, C.c_size_t, vp, _P(vp)]
+    lib.daba_iterate.argtypes = [vp, i, pd]
+    lib.daba_iterate_timed.argtypes = [vp, i, pd]
+    lib.daba_objective.argtypes = [vp, vp, vp, vp, pd]
+    lib.daba_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.daba_get_state.argtypes = [vp, pd, pd, pd, pd, pd, pd]
+    lib.daba_set_state.argtypes = [vp, pd, pd, pd, pd, pd, pd]
+    lib.daba_get_metrics.argtypes = [vp, pd]
+    lib.daba_destroy.argtypes = [vp]
+    lib.daba_last_error.argtypes = [vp]
+    lib.daba_last_error.restype = C.c_char_p
+    for name in ("daba_create", "daba_iterate", "daba_iterate_timed", "daba_objective", "daba_grad",
+                 "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def check(rc: int, where: str, handle=None):
+    if rc != DABA_OK:
+        detail = lib.daba_last_error(handle).decode()
+        raise DabaError(rc, where, detail)

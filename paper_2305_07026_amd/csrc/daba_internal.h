@@ -1,0 +1,131 @@
+// Internal layout shared by the host layer and the gfx950 kernels of the DABA
+// library.  Not part of the ABI.
+//
+// Device data layout (all inside the caller's workspace):
+//  * observations in camera-major order (internal camera id, then internal
+//    landmark id): pixel uv (double2 / float2, internal units), internal
+//    landmark id, landmark-side slot, original index;
+//  * cameras in partition-major order, one 128-byte record each
+//    (R row-major 9 | t 3 | d 3 | pad), three rotating generations
+//    x^(k-1), x^k, x^(k+1) plus the extrapolated x-bar^k and two candidates;
+//  * landmarks in (partition, track length) order; a 64-byte pair record
+//    (l^k xyz, partition id, l^(k-1) xyz, pad) double-buffered, an FP32 copy,
+//    and two candidate buffers;
+//  * landmark-side per-observation records at their slot: groups of up to 64
+//    landmarks with one track length D are stored observation-major
+//    (slot = base + k * n + lane), so the landmark pass reads them coalesced.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace daba {
+
+constexpr int kWave = 64;
+constexpr int kObsWaves = 4;         // waves (tiles) per block of the observation pass
+constexpr int kTileMax = 1024;       // observations per tile (16 per lane)
+constexpr int kMom = 38;             // moments of one surrogate
+constexpr int kTileVals = 80;        // 2 * 38 moments, F share, gap share, pad
+constexpr int kCamRec = 16;          // doubles per camera record
+constexpr int kLmPair = 8;           // doubles per landmark pair record
+constexpr int kCamBlock = 128;       // cameras per block of the camera solve
+constexpr int kLmWaves = 4;          // groups per block of the landmark pass
+constexpr int kMaxPart = 64;
+
+struct DevState {
+    double s;        // s^(k)
+    double gamma;    // gamma^(k) used by the current iteration
+    double F;        // F(x^k) of the last iteration (internal units)
+    int64_t k;
+    int32_t err;     // sticky error code (0 = none)
+    int32_t pad;
+};
+
+// Everything a kernel needs, passed by value.
+struct Params {
+    int64_t M, N, K;
+    int S, T, G;
+    int nCamBlocks, nLmBlocks;
+    int loss;
+    double delta;   // internal units
+    double xi, eta;
+    int accelerate, inner_steps, fp32;
+    uint64_t flags;
+    double scale;
+
+    // observations (camera-major)
+    const double2* uv;
+    const float2* uv32;
+    const int* obs_lm;
+    const int* obs_slot;
+    const int* obs_orig;
+    // tiles
+    const int* tile_cam;
+    const int* tile_begin;
+    const int* tile_end;
+    const int* cam_tile_off;  // [M+1]
+    const int* cam_part;      // [M] internal camera -> partition
+    const int* part_cam;      // [S+1] first internal camera of each partition
+    // landmark groups
+    const int* group_lm0;
+    const int* group_n;
+    const int* group_deg;
+    const int64_t* group_base;
+    const int* lmblock_g0;    // [nLmBlocks]
+    const int* lmblock_g1;
+    const int* camblock_c0;   // [nCamBlocks]
+    const int* camblock_c1;
+    const int* part_camblk;   // [S+1] camera blocks of each partition
+    const int* part_lmblk;    // [S+1] landmark blocks of each partition
+    const int* cam_ext;       // internal -> caller camera index
+    const int* lm_ext;        // internal -> caller landmark index
+
+    // state
+    double* cams[3];
+    double* cam_bar;
+    double* cam_cand[2];      // 0: plain MM, 1: accelerated
+    double* lpair[2];
+    float* lpair32[2];
+    double* lcand[2];
+    double* rec;
+    float* rec32;
+    double* tile_vals;        // [T * kTileVals]
+    double* tile_bins;        // [2S * T], column q*S + beta
+    double* camblk_vals;      // [nCamBlocks * 4]
+    double* lmblk_vals;       // [nLmBlocks * 2]
+    double* colsum;           // [2S]
+    double* Fbar;             // [S] Fbar^a(k-1) -> Fbar^a(k)
+    double* E;                // [S] E^a(k) -> E^a(k+1)
+    double* EE;               // [S] E^a(x^k | x^(k-1))
+    double* Fprev;            // [S] F^a(k-1)
+    int* restart;             // [S]
+    double* metrics;          // [S*4]
+    DevState* st;
+    double* trace;            // [trace_cap]
+    int trace_cap;
+    // scratch for caller-supplied points (objective / gradient)
+    double* tmp_cams;         // [M * kCamRec]
+    double* tmp_lpair;        // [N * kLmPair]
+    double2* tmp_uv;          // [K]
+    double* grad_tile;        // [T * 16]
+};
+
+// Launchers (daba_kernels.hip).  k mod 3 selects the camera generation and
+// k mod 2 the landmark pair buffer.
+hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s);
+hipError_t launch_entity(const Params& p, int k, hipStream_t s);
+hipError_t launch_decide(const Params& p, int k, hipStream_t s);
+hipError_t launch_select(const Params& p, int k, hipStream_t s);
+// Objective shares at (cams, lpair, uv): tile F shares and bins -> Fsh^a and F.
+hipError_t launch_objective(const Params& p, const double* cams, const double* lpair, const double2* uv,
+                            double* part_out /*[S]*/, double* F_out /*[1]*/, hipStream_t s);
+// x-bar^k for cameras from (x^k, x^(k-1)) with gamma read from the state.
+hipError_t launch_extrapolate_cams(const Params& p, int k, hipStream_t s);
+// Caller arrays -> internal scratch (units and order).
+hipError_t launch_import_point(const Params& p, const double* cams, const double* lms, const double* uv,
+                               hipStream_t s);
+hipError_t launch_grad(const Params& p, const double* cams, const double* lpair, const double2* uv,
+                       double* g_cams, double* g_lms, double* g_uv, hipStream_t s);
+
+}  // namespace daba

@@ -1,0 +1,1365 @@
+// gfx950 kernels of one DABA iteration (Fan et al., Algorithm 1, Sec. VI)
+// with every observation majorized (Prop. 1): the surrogate separates per
+// camera and per landmark, and camera partitions act as the devices of the
+// adaptive restart (Sec. V).
+//
+// Per iteration k (r = k mod 3 picks the camera generation, k mod 2 the
+// landmark pair buffer):
+//   k_obs      one wave per camera tile: evaluates every observation at x^k,
+//              at the extrapolated x-bar^k and at x^(k-1); accumulates the
+//              camera moments of both surrogates (FP64), the F share and the
+//              surrogate-gap share; bins the landmark-side shares per
+//              partition; writes the landmark-side record to its slot.
+//   k_entity   camera subproblems (Levenberg-Marquardt on the moments),
+//              landmark closed forms, column sums of the partition bins.
+//   k_decide   per-partition restart metrics and test (eq. Fak, lFak, Eak).
+//   k_select   picks each partition's candidate, rolls the iterates and
+//              extrapolates the cameras for the next iteration.
+//
+// Numerics.  Camera statistics are taken about the linearization point y
+// (Appendix-style moment form): with z = (ux, uy, 1, |u|^2, |u|^4, lambda),
+// Z = sum w z z^T and Y = sum w r^y z^T where r^y = (R p + lambda t - g)|_y =
+// e_w / 2 (the touching identity behind eq. approx0), the camera surrogate is
+//   Phi(c) - Phi(y) = tr(Mx Z Mx^T) + 2 tr(Mx^T Y) + prox,
+// with Mx the 3x6 map z -> R p(d) - R^y p(d^y) + lambda (t - t^y).  Every term
+// is small near y, so no large cancelling sums appear.  The landmark side
+// uses W = sum w lambda^2 and V = sum w lambda e_w: its minimizer is
+// l^y + V / (2W + xi) and its surrogate change is (W + xi/2)|dl|^2 - dl . V.
+#include "daba_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace daba {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <typename R>
+struct CamT {
+    R r[9], t[3], d[3];
+};
+
+template <typename R>
+__device__ __forceinline__ CamT<R> load_cam(const double* __restrict__ c) {
+    CamT<R> o;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o.r[a] = (R)c[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.t[a] = (R)c[9 + a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.d[a] = (R)c[12 + a];
+    return o;
+}
+
+// Robust loss of Assumption 1 (Huber / Welsch widths in internal units).
+template <int LOSS, typename R>
+__device__ __forceinline__ R loss_rho(R s, R delta, R& w) {
+    if constexpr (LOSS == 1) {
+        if (s <= delta * delta) {
+            w = (R)1;
+            return s;
+        }
+        R rs = sqrt(s);
+        w = delta / rs;
+        return (R)2 * delta * rs - delta * delta;
+    } else if constexpr (LOSS == 2) {
+        R d2 = delta * delta;
+        R ex = exp(-s / d2);
+        w = ex;
+        return d2 * ((R)1 - ex);
+    } else {
+        w = (R)1;
+        return s;
+    }
+}
+
+// One observation at camera c and landmark l (Sec. III): the rotated ray Rp,
+// m = l - t, the depth scalar lambda (eq. lambdaij), the world-frame residual
+// e_w = R p - lambda m (= R e of eq. error), |e|^2, the weight w = rho' and rho.
+template <int LOSS, typename R>
+struct ObsEval {
+    R Rp[3], m[3], lam, e[3], s, w, rho, r2;
+};
+
+template <int LOSS, typename R>
+__device__ __forceinline__ void eval_obs(const CamT<R>& c, R l0, R l1, R l2, R ux, R uy, R r2u, R r4u, R delta,
+                                         ObsEval<LOSS, R>& o) {
+    R pz = c.d[0] + c.d[1] * r2u + c.d[2] * r4u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.Rp[a] = c.r[3 * a] * ux + c.r[3 * a + 1] * uy + c.r[3 * a + 2] * pz;
+    o.m[0] = l0 - c.t[0];
+    o.m[1] = l1 - c.t[1];
+    o.m[2] = l2 - c.t[2];
+    o.r2 = o.m[0] * o.m[0] + o.m[1] * o.m[1] + o.m[2] * o.m[2];
+    R inv = (R)1 / o.r2;
+    o.lam = (o.m[0] * o.Rp[0] + o.m[1] * o.Rp[1] + o.m[2] * o.Rp[2]) * inv;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.e[a] = o.Rp[a] - o.lam * o.m[a];
+    o.s = o.e[0] * o.e[0] + o.e[1] * o.e[1] + o.e[2] * o.e[2];
+    o.rho = loss_rho<LOSS, R>(o.s, delta, o.w);
+}
+
+// Moments of one surrogate (see header comment): a[0..19] = Z, a[20..37] = Y.
+template <typename R>
+__device__ __forceinline__ void add_moments(double* a, R w, R lam, R ux, R uy, R r2, R r4, R r6, R r8,
+                                            const R* e) {
+    R wu = w * ux, wv = w * uy, wl = w * lam;
+    a[0] += (double)(wu * ux);
+    a[1] += (double)(wu * uy);
+    a[2] += (double)(wv * uy);
+    a[3] += (double)wu;
+    a[4] += (double)(wu * r2);
+    a[5] += (double)(wu * r4);
+    a[6] += (double)wv;
+    a[7] += (double)(wv * r2);
+    a[8] += (double)(wv * r4);
+    a[9] += (double)w;
+    a[10] += (double)(w * r2);
+    a[11] += (double)(w * r4);
+    a[12] += (double)(w * r6);
+    a[13] += (double)(w * r8);
+    a[14] += (double)(wl * ux);
+    a[15] += (double)(wl * uy);
+    a[16] += (double)wl;
+    a[17] += (double)(wl * r2);
+    a[18] += (double)(wl * r4);
+    a[19] += (double)(wl * lam);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        R g = (R)0.5 * w * e[k];  // w r^y with r^y = e_w / 2
+        a[20 + 6 * k + 0] += (double)(g * ux);
+        a[20 + 6 * k + 1] += (double)(g * uy);
+        a[20 + 6 * k + 2] += (double)g;
+        a[20 + 6 * k + 3] += (double)(g * r2);
+        a[20 + 6 * k + 4] += (double)(g * r4);
+        a[20 + 6 * k + 5] += (double)(g * lam);
+    }
+}
+
+template <typename R>
+struct LmRead {
+    R lk[3], lp[3];
+    int beta;
+};
+
+__device__ __forceinline__ LmRead<double> read_pair(const double* __restrict__ base, int li) {
+    const double2* q = reinterpret_cast<const double2*>(base + (size_t)li * kLmPair);
+    double2 a = q[0], b = q[1], c = q[2], d = q[3];
+    LmRead<double> o;
+    o.lk[0] = a.x; o.lk[1] = a.y; o.lk[2] = b.x;
+    o.beta = (int)__double_as_longlong(b.y);
+    o.lp[0] = c.x; o.lp[1] = c.y; o.lp[2] = d.x;
+    return o;
+}
+
+__device__ __forceinline__ LmRead<float> read_pair(const float* __restrict__ base, int li) {
+    const float4* q = reinterpret_cast<const float4*>(base + (size_t)li * kLmPair);
+    float4 a = q[0], b = q[1];
+    LmRead<float> o;
+    o.lk[0] = a.x; o.lk[1] = a.y; o.lk[2] = a.z;
+    o.beta = __float_as_int(a.w);
+    o.lp[0] = b.x; o.lp[1] = b.y; o.lp[2] = b.z;
+    return o;
+}
+
+__device__ __forceinline__ void write_rec(double* __restrict__ rec, int slot, const double* v) {
+    double4* q = reinterpret_cast<double4*>(rec + (size_t)slot * 8);
+    q[0] = make_double4(v[0], v[1], v[2], v[3]);
+    q[1] = make_double4(v[4], v[5], v[6], v[7]);
+}
+__device__ __forceinline__ void write_rec(float* __restrict__ rec, int slot, const float* v) {
+    float4* q = reinterpret_cast<float4*>(rec + (size_t)slot * 8);
+    q[0] = make_float4(v[0], v[1], v[2], v[3]);
+    q[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_uv(const Params& p, int o, R& ux, R& uy);
+template <>
+__device__ __forceinline__ void load_uv<double>(const Params& p, int o, double& ux, double& uy) {
+    double2 u = p.uv[o];
+    ux = u.x;
+    uy = u.y;
+}
+template <>
+__device__ __forceinline__ void load_uv<float>(const Params& p, int o, float& ux, float& uy) {
+    float2 u = p.uv32[o];
+    ux = u.x;
+    uy = u.y;
+}
+
+template <typename R>
+__device__ __forceinline__ const R* pair_base(const Params& p, int k);
+template <>
+__device__ __forceinline__ const double* pair_base<double>(const Params& p, int k) { return p.lpair[k & 1]; }
+template <>
+__device__ __forceinline__ const float* pair_base<float>(const Params& p, int k) { return p.lpair32[k & 1]; }
+
+template <typename R>
+__device__ __forceinline__ R* rec_base(const Params& p);
+template <>
+__device__ __forceinline__ double* rec_base<double>(const Params& p) { return p.rec; }
+template <>
+__device__ __forceinline__ float* rec_base<float>(const Params& p) { return p.rec32; }
+
+// Segmented sum over lanes whose keys are sorted (equal keys contiguous);
+// the last lane of each run adds the run's sum into bins[key].
+__device__ __forceinline__ void bin_add_sorted(double v0, double v1, int key, int lane, double* bins0,
+                                               double* bins1) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        double o0 = __shfl_up(v0, d, kWave);
+        double o1 = __shfl_up(v1, d, kWave);
+        int ok = __shfl_up(key, d, kWave);
+        if (lane >= d && ok == key) {
+            v0 += o0;
+            v1 += o1;
+        }
+    }
+    int nk = __shfl_down(key, 1, kWave);
+    bool last = (lane == kWave - 1) || (nk != key);
+    if (last && key >= 0) {
+        bins0[key] += v0;
+        bins1[key] += v1;
+    }
+}
+
+// ------------------------------------------------------- observation pass
+
+constexpr int kAcc = 78;   // 2 x 38 moments + F share + gap share
+constexpr int kRedCh = 20; // values per LDS transpose round
+
+template <typename R, int LOSS, bool ACC>
+__global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
+    __shared__ double red[kObsWaves][kRedCh * (kWave + 1)];
+    __shared__ double bins[kObsWaves][2][kMaxPart];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int t = uniform_int(blockIdx.x * kObsWaves + wv);
+    const bool active = t < p.T;
+    const int S = p.S;
+
+    for (int b = lane; b < S; b += kWave) {
+        bins[wv][0][b] = 0.0;
+        bins[wv][1][b] = 0.0;
+    }
+
+    double acc[kAcc];
+#pragma unroll
+    for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
+
+    int beg = 0, end = 0, ci = 0, alpha = 0;
+    if (active) {
+        ci = uniform_int(p.tile_cam[t]);
+        beg = uniform_int(p.tile_begin[t]);
+        end = uniform_int(p.tile_end[t]);
+        alpha = uniform_int(p.cam_part[ci]);
+    }
+    const CamT<R> ck = load_cam<R>(p.cams[k % 3] + (size_t)ci * kCamRec);
+    const CamT<R> cp = load_cam<R>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
+    CamT<R> cb;
+    if constexpr (ACC) cb = load_cam<R>(p.cam_bar + (size_t)ci * kCamRec);
+    const R gam = ACC ? (R)p.st->gamma : (R)0;
+    const R delta = (R)p.delta;
+    const R* __restrict__ pairs = pair_base<R>(p, k);
+    R* __restrict__ rec = rec_base<R>(p);
+    bool bad = false;
+    __syncthreads();
+
+    for (int base = beg; base < end; base += kWave) {
+        const int o = base + lane;
+        const bool on = o < end;
+        double hF = 0.0, gp = 0.0;
+        int key = -1;
+        if (on) {
+            R ux, uy;
+            load_uv<R>(p, o, ux, uy);
+            const int li = p.obs_lm[o];
+            const int slot = p.obs_slot[o];
+            const LmRead<R> L = read_pair(pairs, li);
+            const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
+            const R r6u = r4u * r2u, r8u = r4u * r4u;
+
+            ObsEval<LOSS, R> ek;
+            eval_obs<LOSS, R>(ck, L.lk[0], L.lk[1], L.lk[2], ux, uy, r2u, r4u, delta, ek);
+            bad |= !(ek.r2 > (R)1e-24);
+            add_moments<R>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
+            R rv[8];
+            rv[0] = ek.w * ek.lam * ek.lam;
+            rv[1] = ek.w * ek.lam * ek.e[0];
+            rv[2] = ek.w * ek.lam * ek.e[1];
+            rv[3] = ek.w * ek.lam * ek.e[2];
+            rv[4] = rv[5] = rv[6] = rv[7] = (R)0;
+            if constexpr (ACC) {
+                R lb0 = L.lk[0] + gam * (L.lk[0] - L.lp[0]);
+                R lb1 = L.lk[1] + gam * (L.lk[1] - L.lp[1]);
+                R lb2 = L.lk[2] + gam * (L.lk[2] - L.lp[2]);
+                ObsEval<LOSS, R> eb;
+                eval_obs<LOSS, R>(cb, lb0, lb1, lb2, ux, uy, r2u, r4u, delta, eb);
+                bad |= !(eb.r2 > (R)1e-24);
+                add_moments<R>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
+                rv[4] = eb.w * eb.lam * eb.lam;
+                rv[5] = eb.w * eb.lam * eb.e[0];
+                rv[6] = eb.w * eb.lam * eb.e[1];
+                rv[7] = eb.w * eb.lam * eb.e[2];
+            }
+            write_rec(rec, slot, rv);
+            // F share: each side of the pair gets half of F_ij = rho / 2
+            hF = (double)((R)0.25 * ek.rho);
+            key = L.beta;
+            if (L.beta != alpha) {
+                // surrogate gap of the previous linearization y = x^(k-1) at x^k:
+                // P - Q = w (|Dc|^2 - |Dl|^2 + e^y . (Dc + Dl)) with
+                // Dc = R^k p^k - R^y p^y + lambda^y (t^k - t^y), Dl = lambda^y (l^k - l^y)
+                ObsEval<LOSS, R> ep;
+                eval_obs<LOSS, R>(cp, L.lp[0], L.lp[1], L.lp[2], ux, uy, r2u, r4u, delta, ep);
+                R dc[3], dl[3], q = (R)0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    dc[a] = ek.Rp[a] - ep.Rp[a] + ep.lam * (ck.t[a] - cp.t[a]);
+                    dl[a] = ep.lam * (L.lk[a] - L.lp[a]);
+                    q += dc[a] * dc[a] - dl[a] * dl[a] + ep.e[a] * (dc[a] + dl[a]);
+                }
+                gp = (double)((R)0.5 * ep.w * q);
+            }
+        }
+        acc[2 * kMom] += hF;
+        acc[2 * kMom + 1] += gp;
+        if (S > 1) {
+            bin_add_sorted(hF, -gp, key, lane, bins[wv][0], bins[wv][1]);
+        } else {
+            // one partition: the landmark side of every pair belongs to it
+            double s0 = wave_sum(hF), s1 = wave_sum(-gp);
+            if (lane == 0) {
+                bins[wv][0][0] += s0;
+                bins[wv][1][0] += s1;
+            }
+        }
+    }
+    if (bad) p.st->err = -5;
+
+    // tile totals: LDS transpose, lane v sums value v over the 64 lanes
+    double* rw = red[wv];
+#pragma unroll
+    for (int c0 = 0; c0 < kAcc; c0 += kRedCh) {
+#pragma unroll
+        for (int v = 0; v < kRedCh; ++v)
+            if (c0 + v < kAcc) rw[v * (kWave + 1) + lane] = acc[c0 + v];
+        __syncthreads();
+        if (active && lane < kRedCh && c0 + lane < kAcc) {
+            double s = 0.0;
+            const double* row = rw + lane * (kWave + 1);
+            for (int q = 0; q < kWave; ++q) s += row[q];
+            p.tile_vals[(size_t)t * kTileVals + c0 + lane] = s;
+        }
+        __syncthreads();
+    }
+    if (active) {
+        for (int b = lane; b < S; b += kWave) {
+            p.tile_bins[(size_t)b * p.T + t] = bins[wv][0][b];
+            p.tile_bins[(size_t)(S + b) * p.T + t] = bins[wv][1][b];
+        }
+    }
+}
+
+// ---------------------------------------------------- camera subproblem
+
+struct CamD {
+    double R[9], t[3], d[3];
+};
+
+__device__ __forceinline__ CamD load_camd(const double* __restrict__ c) {
+    CamD o;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o.R[a] = c[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.t[a] = c[9 + a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.d[a] = c[12 + a];
+    return o;
+}
+__device__ __forceinline__ void store_camd(double* __restrict__ c, const CamD& o) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) c[a] = o.R[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[9 + a] = o.t[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[12 + a] = o.d[a];
+    c[15] = 0.0;
+}
+
+// 6x6 symmetric Z from its 20 distinct moments (z = ux, uy, 1, r2, r4, lambda)
+__device__ __forceinline__ void unpack_Z(const double* a, double Z[6][6]) {
+    Z[0][0] = a[0]; Z[0][1] = a[1]; Z[1][1] = a[2];
+    Z[0][2] = a[3]; Z[0][3] = a[4]; Z[0][4] = a[5];
+    Z[1][2] = a[6]; Z[1][3] = a[7]; Z[1][4] = a[8];
+    Z[2][2] = a[9]; Z[2][3] = a[10]; Z[2][4] = a[11];
+    Z[3][3] = a[11]; Z[3][4] = a[12]; Z[4][4] = a[13];
+    Z[0][5] = a[14]; Z[1][5] = a[15];
+    Z[2][5] = a[16]; Z[3][5] = a[17]; Z[4][5] = a[18];
+    Z[5][5] = a[19];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) Z[i][j] = Z[j][i];
+}
+
+// Mx: the 3x6 map z -> R p(d) - Ry p(dy) + lambda (t - ty)
+__device__ __forceinline__ void build_Mx(const CamD& y, const CamD& c, double Mx[3][6]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        Mx[r][0] = c.R[3 * r] - y.R[3 * r];
+        Mx[r][1] = c.R[3 * r + 1] - y.R[3 * r + 1];
+        double dR2 = c.R[3 * r + 2] - y.R[3 * r + 2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Mx[r][2 + k] = c.d[k] * dR2 + (c.d[k] - y.d[k]) * y.R[3 * r + 2];
+        Mx[r][5] = c.t[r] - y.t[r];
+    }
+}
+
+__device__ __forceinline__ double prox2(const CamD& y, const CamD& c) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) s += (c.R[a] - y.R[a]) * (c.R[a] - y.R[a]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s += (c.t[a] - y.t[a]) * (c.t[a] - y.t[a]) + (c.d[a] - y.d[a]) * (c.d[a] - y.d[a]);
+    return s;
+}
+
+// Phi(c) - Phi(y) of one camera's surrogate (moments about y)
+__device__ double phi_delta(const double* mom, const CamD& y, const CamD& c, double xi) {
+    double Z[6][6], Mx[3][6];
+    unpack_Z(mom, Z);
+    build_Mx(y, c, Mx);
+    double q = 0.0, lin = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double za = 0.0;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) za += Z[a][b] * Mx[r][b];
+            q += Mx[r][a] * za;
+            lin += Mx[r][a] * mom[20 + 6 * r + a];
+        }
+    return q + 2.0 * lin + 0.5 * xi * prox2(y, c);
+}
+
+// Gauss-Newton model at c: H = 2 sum w J^T J + xi I (lower triangle, packed)
+// and gradient of the exact surrogate, in tangent coordinates (dtheta, dt, dd)
+// with R <- R Exp(dtheta).
+__device__ void grad_hess(const double* mom, const CamD& y, const CamD& c, double xi, double* Hp, double* g) {
+    double Z[6][6], Mx[3][6];
+    unpack_Z(mom, Z);
+    build_Mx(y, c, Mx);
+    const double* d = c.d;
+    double G00 = Z[0][0], G01 = Z[0][1], G11 = Z[1][1];
+    double G02 = d[0] * Z[0][2] + d[1] * Z[0][3] + d[2] * Z[0][4];
+    double G12 = d[0] * Z[1][2] + d[1] * Z[1][3] + d[2] * Z[1][4];
+    double G22 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G22 += d[a] * d[b] * Z[2 + a][2 + b];
+    double G[3][3] = {{G00, G01, G02}, {G01, G11, G12}, {G02, G12, G22}};
+    double tr = G00 + G11 + G22;
+    double pl[3] = {Z[0][5], Z[1][5], d[0] * Z[2][5] + d[1] * Z[3][5] + d[2] * Z[4][5]};
+    double px[3][3] = {{0, -pl[2], pl[1]}, {pl[2], 0, -pl[0]}, {-pl[1], pl[0], 0}};
+    double H[9][9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            H[a][b] = 2.0 * ((a == b ? tr : 0.0) - G[a][b]);
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) s += px[a][q] * c.R[3 * b + q];
+            H[a][3 + b] = 2.0 * s;
+            H[3 + a][3 + b] = (a == b) ? 2.0 * Z[5][5] : 0.0;
+            H[3 + a][6 + b] = 2.0 * c.R[3 * a + 2] * Z[2 + b][5];
+            H[6 + a][6 + b] = 2.0 * Z[2 + a][2 + b];
+        }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        H[0][6 + b] = 2.0 * Z[1][2 + b];
+        H[1][6 + b] = -2.0 * Z[0][2 + b];
+        H[2][6 + b] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) H[a][a] += xi;
+    int idx = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            // lower triangle from the blocks filled above (upper-right stored)
+            Hp[idx++] = (i / 3 == j / 3) ? H[i][j] : H[j][i];
+        }
+    // residual moments at c: Yc = Y + Mx Z
+    double Yc[3][6];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double s = mom[20 + 6 * r + a];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) s += Mx[r][b] * Z[b][a];
+            Yc[r][a] = s;
+        }
+    double Yp[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        Yp[r][0] = Yc[r][0];
+        Yp[r][1] = Yc[r][1];
+        Yp[r][2] = d[0] * Yc[r][2] + d[1] * Yc[r][3] + d[2] * Yc[r][4];
+    }
+    double W[3][3], Q[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                s += c.R[3 * r + a] * Yp[r][b];
+                s2 += c.R[3 * r + a] * y.R[3 * r + b];
+            }
+            W[a][b] = s;
+            Q[a][b] = s2;
+        }
+    g[0] = 2.0 * (W[2][1] - W[1][2]) - xi * (Q[2][1] - Q[1][2]);
+    g[1] = 2.0 * (W[0][2] - W[2][0]) - xi * (Q[0][2] - Q[2][0]);
+    g[2] = 2.0 * (W[1][0] - W[0][1]) - xi * (Q[1][0] - Q[0][1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[3 + a] = 2.0 * Yc[a][5] + xi * (c.t[a] - y.t[a]);
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2)
+        g[6 + k2] = 2.0 * (c.R[2] * Yc[0][2 + k2] + c.R[5] * Yc[1][2 + k2] + c.R[8] * Yc[2][2 + k2]) +
+                    xi * (c.d[k2] - y.d[k2]);
+}
+
+// (A) x = b for SPD A given as packed lower triangle; false if not SPD
+__device__ bool chol9(double* L, const double* b, double* x) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double s = L[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) s -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i * (i + 1) / 2 + i] = sqrt(s);
+            } else {
+                L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+            }
+        }
+    }
+    double z[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int q = 0; q < i; ++q) s -= L[i * (i + 1) / 2 + q] * z[q];
+        z[i] = s / L[i * (i + 1) / 2 + i];
+    }
+#pragma unroll
+    for (int i = 8; i >= 0; --i) {
+        double s = z[i];
+#pragma unroll
+        for (int q = i + 1; q < 9; ++q) s -= L[q * (q + 1) / 2 + i] * x[q];
+        x[i] = s / L[i * (i + 1) / 2 + i];
+    }
+    return true;
+}
+
+// Rodrigues formula for Exp of the skew matrix of w (Taylor below 1e-8 rad)
+__device__ __forceinline__ void exp_so3(const double* w, double* E) {
+    double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double th = sqrt(th2);
+    double A, B;
+    if (th < 1e-8) {
+        A = 1.0;
+        B = 0.5;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+    }
+    double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double k2 = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+            E[3 * r + c] = (r == c ? 1.0 : 0.0) + A * K[3 * r + c] + B * k2;
+        }
+}
+
+// Levenberg-Marquardt on one camera's surrogate: start at y, mu = 1e-4,
+// accept iff the surrogate strictly decreases (mu /= 10), else mu *= 10,
+// give up after 10 rejects in a row; inner_steps accepted steps (<= 0:
+// until the step is negligible or 100 accepted steps).
+__device__ CamD lm_camera(const double* mom, const CamD& y, double xi, int inner_steps) {
+    CamD c = y;
+    double phi = 0.0;
+    double mu = 1e-4;
+    int succ = 0, rej = 0;
+    for (;;) {
+        if (inner_steps > 0 && succ >= inner_steps) break;
+        if (inner_steps <= 0 && succ >= 100) break;
+        double Hp[45], g[9];
+        grad_hess(mom, y, c, xi, Hp, g);
+        double A[45], rhs[9], dl[9];
+#pragma unroll
+        for (int i = 0; i < 45; ++i) A[i] = Hp[i];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            A[i * (i + 1) / 2 + i] += mu * Hp[i * (i + 1) / 2 + i];
+            rhs[i] = -g[i];
+        }
+        bool ok = chol9(A, rhs, dl);
+        CamD cand = c;
+        double phic = 0.0;
+        if (ok) {
+            double E[9];
+            exp_so3(dl, E);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    cand.R[3 * r + q] = c.R[3 * r] * E[q] + c.R[3 * r + 1] * E[3 + q] + c.R[3 * r + 2] * E[6 + q];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cand.t[a] = c.t[a] + dl[3 + a];
+                cand.d[a] = c.d[a] + dl[6 + a];
+            }
+            phic = phi_delta(mom, y, cand, xi);
+        }
+        if (ok && phic < phi) {
+            double nd = 0.0, nx = 0.0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) nd += dl[a] * dl[a];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nx += c.t[a] * c.t[a] + c.d[a] * c.d[a];
+            c = cand;
+            phi = phic;
+            mu /= 10.0;
+            ++succ;
+            rej = 0;
+            if (inner_steps <= 0 && sqrt(nd) <= 1e-14 * (1.0 + sqrt(nx))) break;
+        } else {
+            mu *= 10.0;
+            if (++rej >= 10) break;
+        }
+    }
+    return c;
+}
+
+// ------------------------------------------- nearest rotation (eq. proj_rot3d)
+// argmax over unit quaternions q of q^T K q with K the 4x4 symmetric matrix
+// for which tr(R(q)^T M) = q^T K q (Bar-Itzhack's quaternion form of the
+// nearest-rotation problem); the top eigenvector comes from cyclic Jacobi.
+__device__ void nearest_rotation(const double* M, double* R) {
+    double K[4][4];
+    K[0][0] = M[0] + M[4] + M[8];
+    K[1][1] = M[0] - M[4] - M[8];
+    K[2][2] = -M[0] + M[4] - M[8];
+    K[3][3] = -M[0] - M[4] + M[8];
+    K[0][1] = K[1][0] = M[7] - M[5];
+    K[0][2] = K[2][0] = M[2] - M[6];
+    K[0][3] = K[3][0] = M[3] - M[1];
+    K[1][2] = K[2][1] = M[1] + M[3];
+    K[1][3] = K[3][1] = M[2] + M[6];
+    K[2][3] = K[3][2] = M[5] + M[7];
+    double V[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, dg = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            dg += K[i][i] * K[i][i];
+#pragma unroll
+            for (int j = i + 1; j < 4; ++j) off += K[i][j] * K[i][j];
+        }
+        if (off <= 1e-34 * dg) break;
+#pragma unroll
+        for (int pp = 0; pp < 3; ++pp)
+#pragma unroll
+            for (int qq = pp + 1; qq < 4; ++qq) {
+                const double apq = K[pp][qq];
+                // symmetric Schur decomposition of the (pp, qq) 2x2 block
+                double cs = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    double tau = (K[qq][qq] - K[pp][pp]) / (2.0 * apq);
+                    double tt = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                             : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                    cs = 1.0 / sqrt(1.0 + tt * tt);
+                    sn = tt * cs;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double kp = K[r][pp], kq = K[r][qq];
+                    K[r][pp] = cs * kp - sn * kq;
+                    K[r][qq] = sn * kp + cs * kq;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double kp = K[pp][r], kq = K[qq][r];
+                    K[pp][r] = cs * kp - sn * kq;
+                    K[qq][r] = sn * kp + cs * kq;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double vp = V[r][pp], vq = V[r][qq];
+                    V[r][pp] = cs * vp - sn * vq;
+                    V[r][qq] = sn * vp + cs * vq;
+                }
+            }
+    }
+    double bl = K[0][0], w = V[0][0], x = V[1][0], yq = V[2][0], z = V[3][0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+        if (K[i][i] > bl) {
+            bl = K[i][i];
+            w = V[0][i];
+            x = V[1][i];
+            yq = V[2][i];
+            z = V[3][i];
+        }
+    double nq = 1.0 / sqrt(w * w + x * x + yq * yq + z * z);
+    w *= nq; x *= nq; yq *= nq; z *= nq;
+    R[0] = w * w + x * x - yq * yq - z * z;
+    R[1] = 2.0 * (x * yq - w * z);
+    R[2] = 2.0 * (x * z + w * yq);
+    R[3] = 2.0 * (x * yq + w * z);
+    R[4] = w * w - x * x + yq * yq - z * z;
+    R[5] = 2.0 * (yq * z - w * x);
+    R[6] = 2.0 * (x * z - w * yq);
+    R[7] = 2.0 * (yq * z + w * x);
+    R[8] = w * w - x * x - yq * yq + z * z;
+}
+
+// ------------------------------------------------------------ entity pass
+
+template <bool ACC>
+__global__ __launch_bounds__(256) void k_entity(Params p, int k) {
+    __shared__ double sred[4][8];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int b = blockIdx.x;
+    const double xi = p.xi;
+
+    if (b < p.nCamBlocks) {
+        // ---- camera subproblems: threads [0,128) plain MM, [128,256) accelerated
+        const int surr = threadIdx.x / kCamBlock;
+        const int ci = p.camblock_c0[b] + (threadIdx.x % kCamBlock);
+        double dv = 0.0, f1 = 0.0, f2 = 0.0;
+        if (ci < p.camblock_c1[b] && (surr == 0 || ACC)) {
+            double mom[kMom];
+#pragma unroll
+            for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
+            const int t0 = p.cam_tile_off[ci], t1 = p.cam_tile_off[ci + 1];
+            const int off = surr == 0 ? 0 : kMom;
+            for (int t = t0; t < t1; ++t) {
+                const double* tv = p.tile_vals + (size_t)t * kTileVals;
+#pragma unroll
+                for (int a = 0; a < kMom; ++a) mom[a] += tv[off + a];
+                f1 += tv[2 * kMom];
+                f2 += tv[2 * kMom + 1];
+            }
+            const CamD ck = load_camd(p.cams[k % 3] + (size_t)ci * kCamRec);
+            const CamD y = surr == 0 ? ck : load_camd(p.cam_bar + (size_t)ci * kCamRec);
+            const CamD c = lm_camera(mom, y, xi, p.inner_steps);
+            store_camd(p.cam_cand[surr] + (size_t)ci * kCamRec, c);
+            if (surr == 1) {
+                // the plain surrogate (about x^k) at the accelerated candidate
+#pragma unroll
+                for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
+                for (int t = t0; t < t1; ++t) {
+                    const double* tv = p.tile_vals + (size_t)t * kTileVals;
+#pragma unroll
+                    for (int a = 0; a < kMom; ++a) mom[a] += tv[a];
+                }
+            }
+            dv = phi_delta(mom, ck, c, xi);
+            if (surr == 1) f1 = f2 = 0.0;
+        }
+        // block sums in a fixed order: (dmm, dacc, F share, gap share)
+        double v0 = surr == 0 ? dv : 0.0, v1 = surr == 1 ? dv : 0.0;
+        v0 = wave_sum(v0);
+        v1 = wave_sum(v1);
+        f1 = wave_sum(f1);
+        f2 = wave_sum(f2);
+        if (lane == 0) {
+            sred[wv][0] = v0;
+            sred[wv][1] = v1;
+            sred[wv][2] = f1;
+            sred[wv][3] = f2;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
+            p.camblk_vals[(size_t)b * 4 + threadIdx.x] = s;
+        }
+        return;
+    }
+    const int lb = b - p.nCamBlocks;
+    if (lb < p.nLmBlocks) {
+        // ---- landmark subproblems: one wave per group of equal track length
+        const int g = p.lmblock_g0[lb] + wv;
+        double dmm = 0.0, dacc = 0.0;
+        if (g < p.lmblock_g1[lb]) {
+            const int n = p.group_n[g], D = p.group_deg[g];
+            const int li = p.group_lm0[g] + lane;
+            const int64_t base = p.group_base[g];
+            if (lane < n) {
+                double W0 = 0, V0[3] = {0, 0, 0}, W1 = 0, V1[3] = {0, 0, 0};
+                if (p.fp32) {
+                    for (int q = 0; q < D; ++q) {
+                        const float4* r = reinterpret_cast<const float4*>(p.rec32 + (size_t)(base + (int64_t)q * n + lane) * 8);
+                        float4 a = r[0];
+                        W0 += a.x; V0[0] += a.y; V0[1] += a.z; V0[2] += a.w;
+                        if (ACC) {
+                            float4 c2 = r[1];
+                            W1 += c2.x; V1[0] += c2.y; V1[1] += c2.z; V1[2] += c2.w;
+                        }
+                    }
+                } else {
+                    for (int q = 0; q < D; ++q) {
+                        const double4* r = reinterpret_cast<const double4*>(p.rec + (size_t)(base + (int64_t)q * n + lane) * 8);
+                        double4 a = r[0];
+                        W0 += a.x; V0[0] += a.y; V0[1] += a.z; V0[2] += a.w;
+                        if (ACC) {
+                            double4 c2 = r[1];
+                            W1 += c2.x; V1[0] += c2.y; V1[1] += c2.z; V1[2] += c2.w;
+                        }
+                    }
+                }
+                const LmRead<double> L = read_pair(p.lpair[k & 1], li);
+                double dl[3], nm = 0.0, dv = 0.0;
+                const double den0 = 2.0 * W0 + xi;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    dl[a] = V0[a] / den0;
+                    nm += dl[a] * dl[a];
+                    dv += dl[a] * V0[a];
+                }
+                dmm = (W0 + 0.5 * xi) * nm - dv;
+                double* cm = p.lcand[0] + (size_t)li * 4;
+                cm[0] = L.lk[0] + dl[0];
+                cm[1] = L.lk[1] + dl[1];
+                cm[2] = L.lk[2] + dl[2];
+                if (ACC) {
+                    const double gam = p.st->gamma;
+                    const double den1 = 2.0 * W1 + xi;
+                    double da[3], na = 0.0, va = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
+                        double la = lbar + V1[a] / den1;
+                        p.lcand[1][(size_t)li * 4 + a] = la;
+                        da[a] = la - L.lk[a];
+                        na += da[a] * da[a];
+                        va += da[a] * V0[a];
+                    }
+                    dacc = (W0 + 0.5 * xi) * na - va;
+                }
+            }
+        }
+        dmm = wave_sum(dmm);
+        dacc = wave_sum(dacc);
+        if (lane == 0) {
+            sred[wv][0] = dmm;
+            sred[wv][1] = dacc;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
+            p.lmblk_vals[(size_t)lb * 2 + threadIdx.x] = s;
+        }
+        return;
+    }
+    // ---- column sums of the per-tile partition bins
+    const int col = b - p.nCamBlocks - p.nLmBlocks;
+    if (col < 2 * p.S) {
+        const double* src = p.tile_bins + (size_t)col * p.T;
+        double s = 0.0;
+        for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
+        s = wave_sum(s);
+        if (lane == 0) sred[wv][0] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) p.colsum[col] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+    }
+}
+
+// ------------------------------------------------------- restart decision
+
+__global__ __launch_bounds__(256) void k_decide(Params p, int k) {
+    __shared__ double sFsh[kMaxPart];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int S = p.S;
+    for (int a = wv; a < S; a += 4) {
+        double c0 = 0, c1 = 0, c2 = 0, c3 = 0, l0 = 0, l1 = 0;
+        for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
+            c0 += p.camblk_vals[(size_t)q * 4 + 0];
+            c1 += p.camblk_vals[(size_t)q * 4 + 1];
+            c2 += p.camblk_vals[(size_t)q * 4 + 2];
+            c3 += p.camblk_vals[(size_t)q * 4 + 3];
+        }
+        for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
+            l0 += p.lmblk_vals[(size_t)q * 2 + 0];
+            l1 += p.lmblk_vals[(size_t)q * 2 + 1];
+        }
+        c0 = wave_sum(c0); c1 = wave_sum(c1); c2 = wave_sum(c2); c3 = wave_sum(c3);
+        l0 = wave_sum(l0); l1 = wave_sum(l1);
+        if (lane == 0) {
+            // E^a(x^k | x^k): each pair's F split in halves between its sides
+            const double Fsh = c2 + p.colsum[a];
+            // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
+            const double V = Fsh + c3 + p.colsum[S + a];
+            const double Fk = p.E[a] + V - p.EE[a];                       // eq. Fak
+            const double Fb = (1.0 - p.eta) * p.Fbar[a] + p.eta * Fk;     // eq. lFak
+            const double dmm = c0 + l0, dacc = c1 + l1;
+            int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                 // eq. Eak test
+            if (p.accelerate && (p.flags & 1)) rs = 0;
+            if (p.accelerate && (p.flags & 2)) rs = 1;
+            const double dch = rs ? dmm : dacc;
+            p.Fprev[a] = Fk;
+            p.Fbar[a] = Fb;
+            p.E[a] = Fk + dch;
+            p.EE[a] = Fsh + dch;
+            p.restart[a] = rs;
+            p.metrics[4 * a + 0] = Fk;
+            p.metrics[4 * a + 1] = Fb;
+            p.metrics[4 * a + 2] = Fk + dch;
+            p.metrics[4 * a + 3] = (double)rs;
+            sFsh[a] = Fsh;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double F = 0.0;
+        for (int a = 0; a < S; ++a) F += sFsh[a];
+        DevState* st = p.st;
+        if (!isfinite(F)) st->err = -4;
+        st->F = F;
+        const int64_t kk = st->k;
+        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
+        // eq. nesterov_scalar: s^(k+1), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
+        const double s1 = (sqrt(4.0 * st->s * st->s + 1.0) + 1.0) / 2.0;
+        const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
+        st->s = s1;
+        st->gamma = p.accelerate ? (s1 - 1.0) / s2 : 0.0;
+        st->k = kk + 1;
+    }
+}
+
+// ------------------------------------------------------- select and roll
+
+__device__ void extrapolate_cam(const double* cn, const double* co, double gam, double* out) {
+    double Mx[9], Rb[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Mx[a] = cn[a] + gam * (cn[a] - co[a]);
+    nearest_rotation(Mx, Rb);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[a] = Rb[a];
+#pragma unroll
+    for (int a = 9; a < 15; ++a) out[a] = cn[a] + gam * (cn[a] - co[a]);
+    out[15] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_select(Params p, int k) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < p.M) {
+        const int ci = (int)i;
+        const int rs = p.accelerate ? p.restart[p.cam_part[ci]] : 1;
+        const double* src = p.cam_cand[rs ? 0 : 1] + (size_t)ci * kCamRec;
+        double* dst = p.cams[(k + 1) % 3] + (size_t)ci * kCamRec;
+        const double* cur = p.cams[k % 3] + (size_t)ci * kCamRec;
+        double cn[16];
+#pragma unroll
+        for (int a = 0; a < 15; ++a) cn[a] = src[a];
+        cn[15] = 0.0;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) dst[a] = cn[a];
+        if (p.accelerate) {
+            double cb[16];
+            extrapolate_cam(cn, cur, p.st->gamma, cb);
+#pragma unroll
+            for (int a = 0; a < 16; ++a) p.cam_bar[(size_t)ci * kCamRec + a] = cb[a];
+        }
+        return;
+    }
+    const int64_t j = i - p.M;
+    if (j < p.N) {
+        const int li = (int)j;
+        const LmRead<double> L = read_pair(p.lpair[k & 1], li);
+        const int rs = p.accelerate ? p.restart[L.beta] : 1;
+        const double* c = p.lcand[rs ? 0 : 1] + (size_t)li * 4;
+        double ln[3] = {c[0], c[1], c[2]};
+        double2* q = reinterpret_cast<double2*>(p.lpair[(k + 1) & 1] + (size_t)li * kLmPair);
+        q[0] = make_double2(ln[0], ln[1]);
+        q[1] = make_double2(ln[2], __longlong_as_double((long long)L.beta));
+        q[2] = make_double2(L.lk[0], L.lk[1]);
+        q[3] = make_double2(L.lk[2], 0.0);
+        if (p.fp32) {
+            float4* f = reinterpret_cast<float4*>(p.lpair32[(k + 1) & 1] + (size_t)li * kLmPair);
+            f[0] = make_float4((float)ln[0], (float)ln[1], (float)ln[2], __int_as_float(L.beta));
+            f[1] = make_float4((float)L.lk[0], (float)L.lk[1], (float)L.lk[2], 0.0f);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_extrapolate_cams(Params p, int k) {
+    const int ci = blockIdx.x * 256 + threadIdx.x;
+    if (ci >= p.M) return;
+    double cb[16];
+    extrapolate_cam(p.cams[k % 3] + (size_t)ci * kCamRec, p.cams[(k + 2) % 3] + (size_t)ci * kCamRec,
+                    p.st->gamma, cb);
+#pragma unroll
+    for (int a = 0; a < 16; ++a) p.cam_bar[(size_t)ci * kCamRec + a] = cb[a];
+}
+
+// ------------------------------------------------------- objective shares
+
+// Per tile: sum of F_ij / 2 over the tile (camera side) and the landmark-side
+// halves binned by landmark partition (or plain totals when bins is null).
+template <typename R, int LOSS>
+__global__ __launch_bounds__(kObsWaves* kWave) void k_objective(Params p, const double* __restrict__ cams,
+                                                                const double* __restrict__ lpair,
+                                                                const double2* __restrict__ uv,
+                                                                double* __restrict__ tile_F, double* __restrict__ bins_out) {
+    __shared__ double bins[kObsWaves][2][kMaxPart];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int t = uniform_int(blockIdx.x * kObsWaves + wv);
+    const bool active = t < p.T;
+    const int S = p.S;
+    for (int b = lane; b < S; b += kWave) bins[wv][0][b] = bins[wv][1][b] = 0.0;
+    __syncthreads();
+    if (!active) return;
+    const int ci = uniform_int(p.tile_cam[t]);
+    const int beg = uniform_int(p.tile_begin[t]), end = uniform_int(p.tile_end[t]);
+    const CamT<R> c = load_cam<R>(cams + (size_t)ci * kCamRec);
+    const R delta = (R)p.delta;
+    double acc = 0.0;
+    bool bad = false;
+    for (int base = beg; base < end; base += kWave) {
+        const int o = base + lane;
+        double hF = 0.0;
+        int key = -1;
+        if (o < end) {
+            const double2 u2 = uv[o];
+            const R ux = (R)u2.x, uy = (R)u2.y;
+            const LmRead<double> L = read_pair(lpair, p.obs_lm[o]);
+            const R r2u = ux * ux + uy * uy;
+            ObsEval<LOSS, R> e;
+            eval_obs<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
+            bad |= !(e.r2 > (R)1e-24);
+            hF = (double)((R)0.25 * e.rho);
+            key = L.beta;
+        }
+        acc += hF;
+        if (bins_out) bin_add_sorted(hF, 0.0, key, lane, bins[wv][0], bins[wv][1]);
+    }
+    if (bad) p.st->err = -5;
+    acc = wave_sum(acc);
+    if (lane == 0) tile_F[t] = acc;
+    if (bins_out)
+        for (int b = lane; b < S; b += kWave) bins_out[(size_t)b * p.T + t] = bins[wv][0][b];
+}
+
+// Fsh^a = sum over the tiles of a's cameras of the camera halves + column sum
+// of a's landmark halves; F = sum_a Fsh^a.  One block, fixed order.
+__global__ __launch_bounds__(256) void k_objective_reduce(Params p, const double* __restrict__ tile_F,
+                                                          const double* __restrict__ bins,
+                                                          double* __restrict__ part_out, double* __restrict__ F_out) {
+    __shared__ double sp[kMaxPart];
+    __shared__ double sw[4];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int S = p.S;
+    if (!bins) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < p.T; t += 256) s += tile_F[t];
+        s = wave_sum(s);
+        if (lane == 0) sw[wv] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) *F_out = 2.0 * (sw[0] + sw[1] + sw[2] + sw[3]);
+        return;
+    }
+    for (int a = wv; a < S; a += 4) {
+        // camera side: tiles of cameras in partition a are contiguous
+        const int t0 = p.cam_tile_off[p.part_cam[a]], t1 = p.cam_tile_off[p.part_cam[a + 1]];
+        double s = 0.0;
+        for (int t = t0 + lane; t < t1; t += kWave) s += tile_F[t];
+        double s2 = 0.0;
+        for (int t = lane; t < p.T; t += kWave) s2 += bins[(size_t)a * p.T + t];
+        s = wave_sum(s);
+        s2 = wave_sum(s2);
+        if (lane == 0) sp[a] = s + s2;
+    }
+    __syncthreads();
+    if (threadIdx.x < S) part_out[threadIdx.x] = sp[threadIdx.x];
+    if (threadIdx.x == 0) {
+        double F = 0.0;
+        for (int a = 0; a < S; ++a) F += sp[a];
+        *F_out = F;
+        if (!isfinite(F)) p.st->err = -4;
+    }
+}
+
+// ------------------------------------------------------------- import point
+
+// Caller arrays (caller order and units) -> internal scratch records.
+__global__ __launch_bounds__(256) void k_import(Params p, const double* __restrict__ cams,
+                                                const double* __restrict__ lms, const double* __restrict__ uv) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double sc = p.scale;
+    if (i < p.M) {
+        const double* src = cams ? cams + (size_t)p.cam_ext[i] * 15 : nullptr;
+        double* dst = p.tmp_cams + (size_t)i * kCamRec;
+        if (src) {
+            for (int a = 0; a < 12; ++a) dst[a] = src[a];
+            dst[12] = src[12] / sc;
+            dst[13] = src[13] * sc;
+            dst[14] = src[14] * sc * sc * sc;
+            dst[15] = 0.0;
+        }
+    }
+    if (i < p.N) {
+        double* dst = p.tmp_lpair + (size_t)i * kLmPair;
+        const double* cur = p.lpair[0];  // partition ids are the same in both buffers
+        const double beta = cur[(size_t)i * kLmPair + 3];
+        if (lms) {
+            const double* src = lms + (size_t)p.lm_ext[i] * 3;
+            dst[0] = src[0];
+            dst[1] = src[1];
+            dst[2] = src[2];
+        }
+        dst[3] = beta;
+    }
+    if (i < p.K && uv) {
+        const int oi = p.obs_orig[i];
+        p.tmp_uv[i] = make_double2(uv[2 * (size_t)oi] / sc, uv[2 * (size_t)oi + 1] / sc);
+    }
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// App. D, eq. DFij: per observation grad_R = -w lambda m e^T (camera-frame e),
+// grad_t = w lambda R e, grad_l = -w lambda R e, grad_d = w e_z (1, |u|^2, |u|^4),
+// grad_u = w (e_xy + e_z (2 d2 + 4 d3 |u|^2) u); camera sums per tile, landmark
+// parts to the observation's slot, pixel parts to the caller's index.
+template <typename R, int LOSS>
+__global__ __launch_bounds__(kObsWaves* kWave) void k_grad_obs(Params p, const double* __restrict__ cams,
+                                                               const double* __restrict__ lpair,
+                                                               const double2* __restrict__ uv,
+                                                               double* __restrict__ g_uv) {
+    __shared__ double red[kObsWaves][16 * (kWave + 1)];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int t = uniform_int(blockIdx.x * kObsWaves + wv);
+    const bool active = t < p.T;
+    double acc[15];
+#pragma unroll
+    for (int a = 0; a < 15; ++a) acc[a] = 0.0;
+    int beg = 0, end = 0, ci = 0;
+    if (active) {
+        ci = uniform_int(p.tile_cam[t]);
+        beg = uniform_int(p.tile_begin[t]);
+        end = uniform_int(p.tile_end[t]);
+    }
+    const CamT<R> c = load_cam<R>(cams + (size_t)ci * kCamRec);
+    const R delta = (R)p.delta;
+    for (int base = beg; base < end; base += kWave) {
+        const int o = base + lane;
+        if (o < end) {
+            const double2 u2 = uv[o];
+            const R ux = (R)u2.x, uy = (R)u2.y;
+            const LmRead<double> L = read_pair(lpair, p.obs_lm[o]);
+            const R r2u = ux * ux + uy * uy;
+            ObsEval<LOSS, R> e;
+            eval_obs<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
+            // camera-frame residual ec = R^T e_w
+            R ec[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ec[a] = c.r[a] * e.e[0] + c.r[3 + a] * e.e[1] + c.r[6 + a] * e.e[2];
+            const R wl = e.w * e.lam;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) acc[3 * a + bb] += (double)(-wl * e.m[a] * ec[bb]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[9 + a] += (double)(wl * e.e[a]);
+            acc[12] += (double)(e.w * ec[2]);
+            acc[13] += (double)(e.w * ec[2] * r2u);
+            acc[14] += (double)(e.w * ec[2] * r2u * r2u);
+            double* lr = p.rec + (size_t)p.obs_slot[o] * 8;
+            lr[0] = (double)(-wl * e.e[0]);
+            lr[1] = (double)(-wl * e.e[1]);
+            lr[2] = (double)(-wl * e.e[2]);
+            if (g_uv) {
+                const R dz = (R)2 * c.d[1] + (R)4 * c.d[2] * r2u;
+                const int oi = p.obs_orig[o];
+                // caller units: dF_px/du_px = s dF/du
+                g_uv[2 * (size_t)oi] = p.scale * (double)(e.w * (ec[0] + ec[2] * dz * ux));
+                g_uv[2 * (size_t)oi + 1] = p.scale * (double)(e.w * (ec[1] + ec[2] * dz * uy));
+            }
+        }
+    }
+    double* rw = red[wv];
+#pragma unroll
+    for (int v = 0; v < 15; ++v) rw[v * (kWave + 1) + lane] = acc[v];
+    __syncthreads();
+    if (active && lane < 15) {
+        double s = 0.0;
+        for (int q = 0; q < kWave; ++q) s += rw[lane * (kWave + 1) + q];
+        p.grad_tile[(size_t)t * 16 + lane] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_grad_entities(Params p, double* __restrict__ g_cams,
+                                                       double* __restrict__ g_lms) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double sc = p.scale, s2 = sc * sc;
+    if (i < p.M && g_cams) {
+        double acc[15];
+#pragma unroll
+        for (int a = 0; a < 15; ++a) acc[a] = 0.0;
+        for (int t = p.cam_tile_off[i]; t < p.cam_tile_off[i + 1]; ++t)
+#pragma unroll
+            for (int a = 0; a < 15; ++a) acc[a] += p.grad_tile[(size_t)t * 16 + a];
+        double* g = g_cams + (size_t)p.cam_ext[i] * 15;
+        for (int a = 0; a < 12; ++a) g[a] = s2 * acc[a];
+        g[12] = s2 * acc[12] / sc;
+        g[13] = s2 * acc[13] * sc;
+        g[14] = s2 * acc[14] * sc * sc * sc;
+    }
+    const int64_t j = i - p.M;
+    if (j >= 0 && j < p.N && g_lms) {
+        // landmark li = j: its slots are in its group
+        const int li = (int)j;
+        // find the group by the per-landmark table packed in group arrays:
+        // groups are contiguous in landmark id; binary search
+        int lo = 0, hi = p.G - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (p.group_lm0[mid] <= li) lo = mid;
+            else hi = mid - 1;
+        }
+        const int g = lo, n = p.group_n[g], D = p.group_deg[g], lane = li - p.group_lm0[g];
+        double a0 = 0, a1 = 0, a2 = 0;
+        for (int q = 0; q < D; ++q) {
+            const double* r = p.rec + (size_t)(p.group_base[g] + (int64_t)q * n + lane) * 8;
+            a0 += r[0];
+            a1 += r[1];
+            a2 += r[2];
+        }
+        double* gl = g_lms + (size_t)p.lm_ext[li] * 3;
+        gl[0] = s2 * a0;
+        gl[1] = s2 * a1;
+        gl[2] = s2 * a2;
+    }
+}
+
+// -------------------------------------------------------------- launchers
+
+#define DABA_LOSS_SWITCH(LOSS_VAR, BODY)        \
+    switch (LOSS_VAR) {                         \
+    case 1: { constexpr int LS = 1; BODY; } break; \
+    case 2: { constexpr int LS = 2; BODY; } break; \
+    default: { constexpr int LS = 0; BODY; } break; \
+    }
+
+hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s) {
+    if (p.T == 0) return hipSuccess;
+    dim3 grid((p.T + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
+    DABA_LOSS_SWITCH(p.loss, {
+        if (p.fp32) {
+            if (p.accelerate) hipLaunchKernelGGL((k_obs<float, LS, true>), grid, block, 0, s, p, k);
+            else hipLaunchKernelGGL((k_obs<float, LS, false>), grid, block, 0, s, p, k);
+        } else {
+            if (p.accelerate) hipLaunchKernelGGL((k_obs<double, LS, true>), grid, block, 0, s, p, k);
+            else hipLaunchKernelGGL((k_obs<double, LS, false>), grid, block, 0, s, p, k);
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_entity(const Params& p, int k, hipStream_t s) {
+    dim3 grid(p.nCamBlocks + p.nLmBlocks + 2 * p.S), block(256);
+    if (p.accelerate) hipLaunchKernelGGL((k_entity<true>), grid, block, 0, s, p, k);
+    else hipLaunchKernelGGL((k_entity<false>), grid, block, 0, s, p, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide(const Params& p, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, p, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const Params& p, int k, hipStream_t s) {
+    const int64_t n = p.M + p.N;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_extrapolate_cams(const Params& p, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_extrapolate_cams, dim3((unsigned)((p.M + 255) / 256)), dim3(256), 0, s, p, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_objective(const Params& p, const double* cams, const double* lpair, const double2* uv,
+                            double* part_out, double* F_out, hipStream_t s) {
+    double* tile_F = p.tile_vals;                       // reuse: T doubles
+    double* bins = part_out ? p.tile_bins : nullptr;    // reuse: S * T doubles
+    if (p.T > 0) {
+        dim3 grid((p.T + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
+        DABA_LOSS_SWITCH(p.loss, {
+            if (p.fp32) hipLaunchKernelGGL((k_objective<float, LS>), grid, block, 0, s, p, cams, lpair, uv, tile_F, bins);
+            else hipLaunchKernelGGL((k_objective<double, LS>), grid, block, 0, s, p, cams, lpair, uv, tile_F, bins);
+        });
+    }
+    hipLaunchKernelGGL(k_objective_reduce, dim3(1), dim3(256), 0, s, p, tile_F, bins, part_out, F_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_point(const Params& p, const double* cams, const double* lms, const double* uv,
+                               hipStream_t s) {
+    int64_t n = p.M;
+    if (p.N > n) n = p.N;
+    if (p.K > n) n = p.K;
+    hipLaunchKernelGGL(k_import, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, cams, lms, uv);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const Params& p, const double* cams, const double* lpair, const double2* uv,
+                       double* g_cams, double* g_lms, double* g_uv, hipStream_t s) {
+    if (p.T > 0) {
+        dim3 grid((p.T + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
+        DABA_LOSS_SWITCH(p.loss, {
+            if (p.fp32) hipLaunchKernelGGL((k_grad_obs<float, LS>), grid, block, 0, s, p, cams, lpair, uv, g_uv);
+            else hipLaunchKernelGGL((k_grad_obs<double, LS>), grid, block, 0, s, p, cams, lpair, uv, g_uv);
+        });
+    }
+    const int64_t n = p.M + p.N;
+    hipLaunchKernelGGL(k_grad_entities, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g_cams, g_lms);
+    return hipGetLastError();
+}
+
+}  // namespace daba
