@@ -1,0 +1,221 @@
+"""Benchmark of the DABA iteration on one MI355X.
+
+One step = one DABA iteration (Algorithm 1's loop body) over the whole
+synthetic problem.  Default workload: 1,000 cameras, 200,000 landmarks,
+~1.6M observations, 8 camera partitions, Huber loss, FP64 (the configuration
+the headline metric is quoted on).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload C2]
+                  [--no-cpu-baseline] [--no-fp32] [--copy-calibration MB]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FP64_VECTOR_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def obs_pass_bytes(sol, layout_T: int, fp32: bool, accelerate: bool) -> float:
+    """Algorithmic bytes one launch of the observation pass must move.
+
+    Per observation (FP64 / FP32-mixed): the pixel (16 / 8), the landmark
+    index and the landmark-side slot (4 + 4), from the landmark pair record
+    l^k, l^(k-1) and the partition id (52 / 28), and the landmark-side record
+    written at the slot (64 / 32; half without acceleration).  Per tile: three
+    camera records read (3 x 120 B), 78 moment / share sums written (624 B)
+    and the partition bins (16 S B)."""
+    per_obs = (8 if fp32 else 16) + 8 + (28 if fp32 else 52)
+    rec = (32 if fp32 else 64) if accelerate else (16 if fp32 else 32)
+    per_obs += rec
+    per_tile = 3 * 120 + 78 * 8 + 16 * sol.S
+    return per_obs * sol.K + per_tile * layout_T
+
+
+def n_tiles(prob) -> int:
+    cnt = __import__("numpy").bincount(prob["obs_camera"], minlength=prob["n_cameras"])
+    return int(sum(-(-int(c) // 1024) for c in cnt))
+
+
+def equal_objective(prob, ms64, ms32, iters, S, make):
+    """Speedup of FP32-mixed over FP64 in time to F_target =
+    F_64 + 1e-4 (F_init - F_64) (the paper's time-to-target metric with
+    Delta = 1e-4), F_64 the FP64 objective after `iters` iterations."""
+    import numpy as np
+    a = make("fp64")
+    F0 = a.objective()
+    F64 = a.iterate(iters)
+    b = make("fp32_mixed")
+    F32 = b.iterate(int(iters * 1.5))
+    target = F64[-1] + 1e-4 * (F0 - F64[-1])
+    n64 = int(np.argmax(F64 <= target)) + 1 if np.any(F64 <= target) else None
+    n32 = int(np.argmax(F32 <= target)) + 1 if np.any(F32 <= target) else None
+    out = dict(F_init=F0, F_fp64_final=float(F64[-1]), F_target=float(target), iters_fp64=n64, iters_fp32=n32,
+               fp32_rel_err_at_fp64_final_iter=float(abs(F32[iters - 1] - F64[-1]) / F64[-1]))
+    if n64 and n32:
+        out["time_fp64_ms"] = n64 * ms64
+        out["time_fp32_ms"] = n32 * ms32
+        out["speedup_fp32_vs_fp64"] = (n64 * ms64) / (n32 * ms32)
+    else:
+        out["speedup_fp32_vs_fp64"] = None
+    return out
+
+
+def cpu_baseline(prob, S, budget_s=15.0):
+    """The oracle, as it stands, on the same problem and options: whole
+    iterations from x^0 until about budget_s of CPU work has been done."""
+    from oracle import Oracle, num_threads
+    o = Oracle(prob, n_partitions=S, loss="huber", delta=1.0, xi=1e-9, eta=0.5)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.iterate(1)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or n >= 200:
+            break
+    return dict(value=prob["n_obs"] * n / dt, unit="obs*iter/s", cores=num_threads(), kind="oracle",
+                sample=f"{n} oracle iteration(s) of the same {prob['n_obs']}-observation problem from x^0, "
+                       f"{dt:.1f} s wall, OpenMP over entities")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a device copy of this many MiB (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU path is not "
+              "part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from synth import CONFIGS, make_problem
+    import paper_2305_07026_amd as P
+
+    cfg = CONFIGS[args.workload]
+    S = cfg["n_partitions"]
+    log(f"generating {args.workload}")
+    prob = make_problem(args.workload)
+    K = prob["n_obs"]
+    T = n_tiles(prob)
+    opts = dict(n_partitions=S, loss="huber", delta=1.0, xi=1e-9, eta=0.5, accelerate=True, inner_steps=1)
+
+    def make(prec):
+        return P.DabaSolver(prob, precision=prec, **opts)
+
+    log("create")
+    t0 = time.perf_counter()
+    sol = make(args.precision)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    log(f"warmup {args.warmup}")
+    sol.iterate(args.warmup, trace=False)
+    torch.cuda.synchronize()
+    stream = sol.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"timed {args.steps}")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    sol.iterate(args.steps, trace=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / args.steps
+    value = K * args.steps / (gpu_ms / 1e3)
+
+    # per-kernel durations from HIP events around each launch, over the same
+    # number of steps of the same run (instrumented launches, no graph)
+    log("kernel timing")
+    kern = sol.iterate_timed(args.steps) / args.steps
+    fp32 = args.precision == "fp32_mixed"
+    nbytes = obs_pass_bytes(sol, T, fp32, True)
+    achieved = nbytes / (kern[0] / 1e3) / 1e9
+    F_final = sol.objective()
+
+    out = {
+        "metric": "observation-iterations/s and HBM GB/s (FP32-mixed vs FP64) at equal final objective",
+        "value": value,
+        "unit": "obs*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if fp32 else "f64",
+        "data": "synthetic (seeded generator standing in for the paper's BAL/1DSfM scenes)",
+        "config": {"workload": f"{args.workload}: {prob['n_cameras']} cameras, {prob['n_landmarks']} landmarks, "
+                               f"{K} observations, {S} camera partitions, Huber delta=1px, DABA (Nesterov + "
+                               f"adaptive restart), 1 inner LM step, {args.precision}",
+                   "n_cameras": prob["n_cameras"], "n_landmarks": prob["n_landmarks"], "n_obs": K,
+                   "n_partitions": S, "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": "k_obs (observation pass)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": nbytes,
+                     "avg_launch_ms": kern[0]},
+        "kernel_ms_per_step": {"k_obs": kern[0], "k_entity": kern[1], "k_select": kern[2]},
+        "wall_s_timed_region": wall,
+        "setup_s": setup_s,
+        "F_after": F_final,
+    }
+    if not args.no_fp32 and args.precision == "fp64":
+        log("fp32-mixed")
+        s32 = make("fp32_mixed")
+        s32.iterate(args.warmup, trace=False)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(s32.stream)
+        s32.iterate(args.steps, trace=False)
+        f1.record(s32.stream)
+        torch.cuda.synchronize()
+        ms32 = f0.elapsed_time(f1) / args.steps
+        k32 = s32.iterate_timed(args.steps) / args.steps
+        b32 = obs_pass_bytes(s32, T, True, True)
+        del s32
+        log("equal objective")
+        eq = equal_objective(prob, ms_per_step, ms32, cfg["iterations"] or 200, S, make)
+        out["fp32_mixed"] = {"value": K / (ms32 / 1e3), "ms_per_step": ms32,
+                             "k_obs_ms": k32[0], "k_obs_GBs": b32 / (k32[0] / 1e3) / 1e9,
+                             "equal_objective": eq}
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * n * 8
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(prob, S)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

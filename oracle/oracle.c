@@ -229,7 +229,7 @@ static void jacobi3(const double *Ain, double *ev, double *V) {
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
         double diag = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
-        if (off <= 1e-36 * diag || off == 0.0) break;
+        if (off <= 1e-30 * diag || off == 0.0) break; /* off-diagonal at rounding level */
         for (int p = 0; p < 2; ++p)
             for (int q = p + 1; q < 3; ++q) {
                 double apq = A[3 * p + q];

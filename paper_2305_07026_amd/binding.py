@@ -57,6 +57,11 @@ def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                           "python paper_2305_07026_amd/build.py")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one; load it first so that libdaba.so binds to the runtime that owns
+    # the device memory and streams it is handed.
+    import torch  # noqa: F401
+
     lib = C.CDLL(LIB_PATH)
     vp, d, i = C.c_void_p, C.c_double, C.c_int
     pd = _P(d)

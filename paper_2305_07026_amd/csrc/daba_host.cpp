@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -351,6 +352,14 @@ struct daba_handle {
     int64_t k = 0;
     double* d_obj = nullptr;  // [S+1] device scratch for objective outputs
     std::string err = "no error";
+    // six iterations (one period of the buffer rotation) as a HIP graph
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t period = nullptr;
+    bool graphs = true;
+    ~daba_handle() {
+        if (period) hipGraphExecDestroy(period);
+        if (cap_stream) hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace {
@@ -511,9 +520,18 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         if (!(prob->unit_scale > 0.0 && std::isfinite(prob->unit_scale))) fail(DABA_E_INVAL, "unit_scale must be positive");
         for (int64_t o = 0; o < 2 * prob->n_obs; ++o)
             if (!std::isfinite(prob->obs_uv[o])) fail(DABA_E_INVAL, "obs_uv has a non-finite entry");
+        for (int64_t i = 0; i < prob->n_cameras; ++i) {
+            const double* c = prob->cameras + 15 * (size_t)i;
+            for (int a = 0; a < 15; ++a)
+                if (!std::isfinite(c[a])) fail(DABA_E_INVAL, "camera %lld has a non-finite entry", (long long)i);
+            if (!rotation_ok(c)) fail(DABA_E_INVAL, "camera %lld: R is not a rotation", (long long)i);
+        }
+        for (int64_t j = 0; j < 3 * prob->n_landmarks; ++j)
+            if (!std::isfinite(prob->landmarks[j])) fail(DABA_E_INVAL, "landmarks have a non-finite entry");
         h = new daba_handle();
         h->opt = *opt;
         h->stream = (hipStream_t)hip_stream;
+        if (const char* ng = std::getenv("DABA_NO_GRAPH")) h->graphs = !(ng[0] == '1');
         build_layout(prob, h->L);
         const Layout& L = h->L;
         const bool fp32 = opt->precision == DABA_FP32_MIXED;
@@ -608,6 +626,29 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
     }
 }
 
+static void launch_iteration(const Params& p, int k, hipStream_t s) {
+    hipcheck(launch_obs_pass(p, k, s), "k_obs");
+    hipcheck(launch_entity(p, k, s), "k_entity");
+    hipcheck(launch_decide(p, k, s), "k_decide");
+    hipcheck(launch_select(p, k, s), "k_select");
+}
+
+// Captures iterations with k mod 6 = 0..5 once; replaying the graph runs one
+// full period of the buffer rotation.
+static bool ensure_period_graph(daba_handle* h) {
+    if (h->period) return true;
+    if (!h->graphs) return false;
+    hipcheck(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hipcheck(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    for (int k = 0; k < 6; ++k) launch_iteration(h->p, k, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipcheck(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
+    hipError_t e = hipGraphInstantiate(&h->period, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    hipcheck(e, "hipGraphInstantiate");
+    return true;
+}
+
 static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     if (n < 0) fail(DABA_E_INVAL, "n_iters < 0");
     Params& p = h->p;
@@ -619,36 +660,41 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     int pooled = 0;
     auto drain = [&]() {
         if (pooled == 0) return;
-        hipcheck(hipEventSynchronize(ev[5 * (pooled - 1) + 4]), "event sync");
+        hipcheck(hipEventSynchronize(ev[4 * (pooled - 1) + 3]), "event sync");
         for (int q = 0; q < pooled; ++q)
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 3; ++e) {
                 float t = 0.f;
-                hipcheck(hipEventElapsedTime(&t, ev[5 * q + e], ev[5 * q + e + 1]), "elapsed");
+                hipcheck(hipEventElapsedTime(&t, ev[4 * q + e], ev[4 * q + e + 1]), "elapsed");
                 ms[e] += t;
             }
         pooled = 0;
     };
     if (ms) {
-        ev.resize(5 * kPool);
+        ev.resize(4 * kPool);
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
-        for (int e = 0; e < 4; ++e) ms[e] = 0.0;
+        for (int e = 0; e < 3; ++e) ms[e] = 0.0;
     }
     int done = 0;
     while (done < n) {
         const int chunk = std::min(n - done, kTraceCap - 1);
         for (int it = 0; it < chunk; ++it) {
+            if (!ms && h->k % 6 == 0 && chunk - it >= 6 && ensure_period_graph(h)) {
+                hipcheck(hipGraphLaunch(h->period, s), "hipGraphLaunch");
+                h->k += 6;
+                it += 5;
+                continue;
+            }
             const int k = (int)(h->k % 6);
-            hipEvent_t* e5 = ms ? &ev[5 * pooled] : nullptr;
+            hipEvent_t* e5 = ms ? &ev[4 * pooled] : nullptr;
             if (ms) hipcheck(hipEventRecord(e5[0], s), "event");
             hipcheck(launch_obs_pass(p, k, s), "k_obs");
             if (ms) hipcheck(hipEventRecord(e5[1], s), "event");
             hipcheck(launch_entity(p, k, s), "k_entity");
-            if (ms) hipcheck(hipEventRecord(e5[2], s), "event");
             hipcheck(launch_decide(p, k, s), "k_decide");
-            if (ms) hipcheck(hipEventRecord(e5[3], s), "event");
+            if (ms) hipcheck(hipEventRecord(e5[2], s), "event");
             hipcheck(launch_select(p, k, s), "k_select");
             if (ms) {
-                hipcheck(hipEventRecord(e5[4], s), "event");
+                hipcheck(hipEventRecord(e5[3], s), "event");
                 if (++pooled == kPool) drain();
             }
             h->k++;

@@ -664,7 +664,45 @@ __device__ CamD lm_camera(const double* mom, const CamD& y, double xi, int inner
 }
 
 // ------------------------------------------- nearest rotation (eq. proj_rot3d)
-// argmax over unit quaternions q of q^T K q with K the 4x4 symmetric matrix
+// For det(M) > 0 the nearest rotation is the orthogonal polar factor of M,
+// reached by Newton's iteration X <- (X + X^-T) / 2 (quadratic convergence;
+// extrapolated rotations are close to orthogonal, so a few steps suffice).
+__device__ bool polar_rotation(const double* M, double* R) {
+    double X[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) X[a] = M[a];
+    for (int it = 0; it < 16; ++it) {
+        // cofactors of X: X^-T = cof(X) / det(X)
+        double C[9];
+        C[0] = X[4] * X[8] - X[5] * X[7];
+        C[1] = X[5] * X[6] - X[3] * X[8];
+        C[2] = X[3] * X[7] - X[4] * X[6];
+        C[3] = X[2] * X[7] - X[1] * X[8];
+        C[4] = X[0] * X[8] - X[2] * X[6];
+        C[5] = X[1] * X[6] - X[0] * X[7];
+        C[6] = X[1] * X[5] - X[2] * X[4];
+        C[7] = X[2] * X[3] - X[0] * X[5];
+        C[8] = X[0] * X[4] - X[1] * X[3];
+        const double det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+        if (!(det > 0.0)) return false;
+        const double id = 1.0 / det;
+        double ch = 0.0;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const double y = 0.5 * (X[a] + C[a] * id);
+            ch += (y - X[a]) * (y - X[a]);
+            X[a] = y;
+        }
+        if (ch <= 1e-30) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) R[a] = X[a];
+            return true;
+        }
+    }
+    return false;
+}
+
+// General case (any det): argmax over unit quaternions q of q^T K q with K the 4x4 symmetric matrix
 // for which tr(R(q)^T M) = q^T K q (Bar-Itzhack's quaternion form of the
 // nearest-rotation problem); the top eigenvector comes from cyclic Jacobi.
 __device__ void nearest_rotation(const double* M, double* R) {
@@ -684,7 +722,7 @@ __device__ void nearest_rotation(const double* M, double* R) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 16; ++sweep) {
+    for (int sweep = 0; sweep < 12; ++sweep) {
         double off = 0.0, dg = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -692,7 +730,8 @@ __device__ void nearest_rotation(const double* M, double* R) {
 #pragma unroll
             for (int j = i + 1; j < 4; ++j) off += K[i][j] * K[i][j];
         }
-        if (off <= 1e-34 * dg) break;
+        // off-diagonal at the rounding level of the diagonal
+        if (off <= 1e-30 * dg) break;
 #pragma unroll
         for (int pp = 0; pp < 3; ++pp)
 #pragma unroll
@@ -751,6 +790,75 @@ __device__ void nearest_rotation(const double* M, double* R) {
 }
 
 // ------------------------------------------------------------ entity pass
+
+// ------------------------------------------------------- restart decision
+
+// One block, after k_entity: per-partition restart metrics and test, the
+// objective trace and the Nesterov scalars.  (A separate launch: a
+// last-block-done decision inside k_entity needs a device-scope release fence
+// in every block, which writes back the whole L2 of each XCD and costs more
+// than the launch.)
+__global__ __launch_bounds__(256) void k_decide(Params p, int k) {
+    __shared__ double sFsh[kMaxPart];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int S = p.S;
+    for (int a = wv; a < S; a += 4) {
+        double c0 = 0, c1 = 0, c2 = 0, c3 = 0, l0 = 0, l1 = 0;
+        for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
+            c0 += p.camblk_vals[(size_t)q * 4 + 0];
+            c1 += p.camblk_vals[(size_t)q * 4 + 1];
+            c2 += p.camblk_vals[(size_t)q * 4 + 2];
+            c3 += p.camblk_vals[(size_t)q * 4 + 3];
+        }
+        for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
+            l0 += p.lmblk_vals[(size_t)q * 2 + 0];
+            l1 += p.lmblk_vals[(size_t)q * 2 + 1];
+        }
+        c0 = wave_sum(c0); c1 = wave_sum(c1); c2 = wave_sum(c2); c3 = wave_sum(c3);
+        l0 = wave_sum(l0); l1 = wave_sum(l1);
+        if (lane == 0) {
+            // E^a(x^k | x^k): each pair's F split in halves between its sides
+            const double Fsh = c2 + p.colsum[a];
+            // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
+            const double V = Fsh + c3 + p.colsum[S + a];
+            const double Fk = p.E[a] + V - p.EE[a];                       // eq. Fak
+            const double Fb = (1.0 - p.eta) * p.Fbar[a] + p.eta * Fk;     // eq. lFak
+            const double dmm = c0 + l0, dacc = c1 + l1;
+            int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                 // eq. Eak test
+            if (p.accelerate && (p.flags & 1)) rs = 0;
+            if (p.accelerate && (p.flags & 2)) rs = 1;
+            const double dch = rs ? dmm : dacc;
+            p.Fprev[a] = Fk;
+            p.Fbar[a] = Fb;
+            p.E[a] = Fk + dch;
+            p.EE[a] = Fsh + dch;
+            p.restart[a] = rs;
+            p.metrics[4 * a + 0] = Fk;
+            p.metrics[4 * a + 1] = Fb;
+            p.metrics[4 * a + 2] = Fk + dch;
+            p.metrics[4 * a + 3] = (double)rs;
+            sFsh[a] = Fsh;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double F = 0.0;
+        for (int a = 0; a < S; ++a) F += sFsh[a];
+        DevState* st = p.st;
+        if (!isfinite(F) && st->err == 0) st->err = -4;  // a degenerate point reported first wins
+        st->F = F;
+        const int64_t kk = st->k;
+        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
+        // eq. nesterov_scalar: s^(k+1), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
+        const double s1 = (sqrt(4.0 * st->s * st->s + 1.0) + 1.0) / 2.0;
+        const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
+        st->s = s1;
+        st->gamma = p.accelerate ? (s1 - 1.0) / s2 : 0.0;
+        st->k = kk + 1;
+    }
+}
+
 
 template <bool ACC>
 __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
@@ -813,10 +921,8 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
             for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
             p.camblk_vals[(size_t)b * 4 + threadIdx.x] = s;
         }
-        return;
-    }
-    const int lb = b - p.nCamBlocks;
-    if (lb < p.nLmBlocks) {
+    } else if (b - p.nCamBlocks < p.nLmBlocks) {
+        const int lb = b - p.nCamBlocks;
         // ---- landmark subproblems: one wave per group of equal track length
         const int g = p.lmblock_g0[lb] + wv;
         double dmm = 0.0, dacc = 0.0;
@@ -826,24 +932,44 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
             const int64_t base = p.group_base[g];
             if (lane < n) {
                 double W0 = 0, V0[3] = {0, 0, 0}, W1 = 0, V1[3] = {0, 0, 0};
-                if (p.fp32) {
-                    for (int q = 0; q < D; ++q) {
-                        const float4* r = reinterpret_cast<const float4*>(p.rec32 + (size_t)(base + (int64_t)q * n + lane) * 8);
-                        float4 a = r[0];
-                        W0 += a.x; V0[0] += a.y; V0[1] += a.z; V0[2] += a.w;
-                        if (ACC) {
-                            float4 c2 = r[1];
-                            W1 += c2.x; V1[0] += c2.y; V1[1] += c2.z; V1[2] += c2.w;
+                // eight records in flight per lane before they are summed
+                constexpr int U = 8;
+                for (int q0 = 0; q0 < D; q0 += U) {
+                    if (p.fp32) {
+                        float4 ra[U], rb[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            if (q0 + u < D) {
+                                const float4* r = reinterpret_cast<const float4*>(
+                                    p.rec32 + (size_t)(base + (int64_t)(q0 + u) * n + lane) * 8);
+                                ra[u] = r[0];
+                                if (ACC) rb[u] = r[1];
+                            }
                         }
-                    }
-                } else {
-                    for (int q = 0; q < D; ++q) {
-                        const double4* r = reinterpret_cast<const double4*>(p.rec + (size_t)(base + (int64_t)q * n + lane) * 8);
-                        double4 a = r[0];
-                        W0 += a.x; V0[0] += a.y; V0[1] += a.z; V0[2] += a.w;
-                        if (ACC) {
-                            double4 c2 = r[1];
-                            W1 += c2.x; V1[0] += c2.y; V1[1] += c2.z; V1[2] += c2.w;
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            if (q0 + u < D) {
+                                W0 += ra[u].x; V0[0] += ra[u].y; V0[1] += ra[u].z; V0[2] += ra[u].w;
+                                if (ACC) { W1 += rb[u].x; V1[0] += rb[u].y; V1[1] += rb[u].z; V1[2] += rb[u].w; }
+                            }
+                        }
+                    } else {
+                        double4 ra[U], rb[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            if (q0 + u < D) {
+                                const double4* r = reinterpret_cast<const double4*>(
+                                    p.rec + (size_t)(base + (int64_t)(q0 + u) * n + lane) * 8);
+                                ra[u] = r[0];
+                                if (ACC) rb[u] = r[1];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            if (q0 + u < D) {
+                                W0 += ra[u].x; V0[0] += ra[u].y; V0[1] += ra[u].z; V0[2] += ra[u].w;
+                                if (ACC) { W1 += rb[u].x; V1[0] += rb[u].y; V1[1] += rb[u].z; V1[2] += rb[u].w; }
+                            }
                         }
                     }
                 }
@@ -890,11 +1016,9 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
             for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
             p.lmblk_vals[(size_t)lb * 2 + threadIdx.x] = s;
         }
-        return;
-    }
-    // ---- column sums of the per-tile partition bins
-    const int col = b - p.nCamBlocks - p.nLmBlocks;
-    if (col < 2 * p.S) {
+    } else {
+        // ---- column sums of the per-tile partition bins
+        const int col = b - p.nCamBlocks - p.nLmBlocks;
         const double* src = p.tile_bins + (size_t)col * p.T;
         double s = 0.0;
         for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
@@ -905,76 +1029,13 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
     }
 }
 
-// ------------------------------------------------------- restart decision
-
-__global__ __launch_bounds__(256) void k_decide(Params p, int k) {
-    __shared__ double sFsh[kMaxPart];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int S = p.S;
-    for (int a = wv; a < S; a += 4) {
-        double c0 = 0, c1 = 0, c2 = 0, c3 = 0, l0 = 0, l1 = 0;
-        for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
-            c0 += p.camblk_vals[(size_t)q * 4 + 0];
-            c1 += p.camblk_vals[(size_t)q * 4 + 1];
-            c2 += p.camblk_vals[(size_t)q * 4 + 2];
-            c3 += p.camblk_vals[(size_t)q * 4 + 3];
-        }
-        for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
-            l0 += p.lmblk_vals[(size_t)q * 2 + 0];
-            l1 += p.lmblk_vals[(size_t)q * 2 + 1];
-        }
-        c0 = wave_sum(c0); c1 = wave_sum(c1); c2 = wave_sum(c2); c3 = wave_sum(c3);
-        l0 = wave_sum(l0); l1 = wave_sum(l1);
-        if (lane == 0) {
-            // E^a(x^k | x^k): each pair's F split in halves between its sides
-            const double Fsh = c2 + p.colsum[a];
-            // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
-            const double V = Fsh + c3 + p.colsum[S + a];
-            const double Fk = p.E[a] + V - p.EE[a];                       // eq. Fak
-            const double Fb = (1.0 - p.eta) * p.Fbar[a] + p.eta * Fk;     // eq. lFak
-            const double dmm = c0 + l0, dacc = c1 + l1;
-            int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                 // eq. Eak test
-            if (p.accelerate && (p.flags & 1)) rs = 0;
-            if (p.accelerate && (p.flags & 2)) rs = 1;
-            const double dch = rs ? dmm : dacc;
-            p.Fprev[a] = Fk;
-            p.Fbar[a] = Fb;
-            p.E[a] = Fk + dch;
-            p.EE[a] = Fsh + dch;
-            p.restart[a] = rs;
-            p.metrics[4 * a + 0] = Fk;
-            p.metrics[4 * a + 1] = Fb;
-            p.metrics[4 * a + 2] = Fk + dch;
-            p.metrics[4 * a + 3] = (double)rs;
-            sFsh[a] = Fsh;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double F = 0.0;
-        for (int a = 0; a < S; ++a) F += sFsh[a];
-        DevState* st = p.st;
-        if (!isfinite(F)) st->err = -4;
-        st->F = F;
-        const int64_t kk = st->k;
-        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
-        // eq. nesterov_scalar: s^(k+1), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
-        const double s1 = (sqrt(4.0 * st->s * st->s + 1.0) + 1.0) / 2.0;
-        const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
-        st->s = s1;
-        st->gamma = p.accelerate ? (s1 - 1.0) / s2 : 0.0;
-        st->k = kk + 1;
-    }
-}
-
 // ------------------------------------------------------- select and roll
 
 __device__ void extrapolate_cam(const double* cn, const double* co, double gam, double* out) {
     double Mx[9], Rb[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) Mx[a] = cn[a] + gam * (cn[a] - co[a]);
-    nearest_rotation(Mx, Rb);
+    if (!polar_rotation(Mx, Rb)) nearest_rotation(Mx, Rb);
 #pragma unroll
     for (int a = 0; a < 9; ++a) out[a] = Rb[a];
 #pragma unroll
@@ -1119,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_objective_reduce(Params p, const double
         double F = 0.0;
         for (int a = 0; a < S; ++a) F += sp[a];
         *F_out = F;
-        if (!isfinite(F)) p.st->err = -4;
+        if (!isfinite(F) && p.st->err == 0) p.st->err = -4;
     }
 }
 

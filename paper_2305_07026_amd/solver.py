@@ -106,8 +106,8 @@ class DabaSolver:
 
     def iterate_timed(self, n: int):
         """n iterations; returns summed GPU ms of (observation pass, entity
-        solves, restart test, selection)."""
-        ms = np.zeros(4)
+        solves with the restart test, selection)."""
+        ms = np.zeros(3)
         self._chk(B.lib.daba_iterate_timed(self._h, n, _ptr(ms, C.c_double)), "daba_iterate_timed")
         return ms
 

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, it
+exports every function include/daba.h declares, the workspace size is
+computed on the host, and invalid problems are rejected before any device
+work."""
+
+import ctypes as C
+import subprocess
+
+import numpy as np
+import pytest
+
+from synth import make_problem
+
+B = pytest.importorskip("paper_2305_07026_amd.binding")
+
+
+def _problem(prob, **over):
+    keep = dict(cam=np.ascontiguousarray(prob["obs_camera"], np.int32),
+                lm=np.ascontiguousarray(prob["obs_landmark"], np.int32),
+                uv=np.ascontiguousarray(prob["obs_uv"], np.float64),
+                cams=np.ascontiguousarray(prob["cameras"], np.float64),
+                lms=np.ascontiguousarray(prob["landmarks"], np.float64))
+    keep.update(over)
+    P = C.POINTER
+    st = B.DabaProblem(prob["n_cameras"], prob["n_landmarks"], keep["cam"].size,
+                       keep["cam"].ctypes.data_as(P(C.c_int32)), keep["lm"].ctypes.data_as(P(C.c_int32)),
+                       keep["uv"].ctypes.data_as(P(C.c_double)), keep["cams"].ctypes.data_as(P(C.c_double)),
+                       keep["lms"].ctypes.data_as(P(C.c_double)), over.get("S", 4), None, None, 512.0)
+    return st, keep
+
+
+def _opts(**kw):
+    d = dict(loss=1, loss_delta=1.0, xi=1e-9, eta=0.5, accelerate=1, inner_steps=1, precision=0, debug_flags=0)
+    d.update(kw)
+    return B.DabaOptions(**d)
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return make_problem("C1", n_cameras=12, n_landmarks=300, seed=21)
+
+
+def test_exports_every_declared_function():
+    names = B.header_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(B.lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_workspace_bytes_on_host(prob):
+    st, _keep = _problem(prob)
+    n64 = B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts()))
+    n32 = B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts(precision=1)))
+    assert n64 > 0 and n32 > n64  # the mixed form keeps FP32 copies besides the FP64 state
+    big = make_problem("C1", n_cameras=12, n_landmarks=900, seed=21)
+    st2, _k2 = _problem(big)
+    assert B.lib.daba_workspace_bytes(C.byref(st2), C.byref(_opts())) > n64
+    assert B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts(eta=0.0))) == 0
+
+
+@pytest.mark.parametrize("case", ["bad_index", "nan_uv", "not_rotation", "bad_partitions", "bad_xi",
+                                  "degenerate", "null_workspace"])
+def test_create_rejects_before_device_work(prob, case):
+    over, opts, ws = {}, _opts(), C.c_void_p(4096)
+    if case == "bad_index":
+        cam = np.ascontiguousarray(prob["obs_camera"], np.int32).copy()
+        cam[3] = prob["n_cameras"]
+        over["cam"] = cam
+    elif case == "nan_uv":
+        uv = prob["obs_uv"].copy()
+        uv[5, 1] = np.nan
+        over["uv"] = uv
+    elif case == "not_rotation":
+        cams = prob["cameras"].copy()
+        cams[2, :9] *= 1.01
+        over["cams"] = cams
+    elif case == "bad_partitions":
+        over["S"] = 65
+    elif case == "bad_xi":
+        opts = _opts(xi=0.0)
+    elif case == "degenerate":
+        lms = prob["landmarks"].copy()
+        j = prob["obs_landmark"][0]
+        lms[j] = prob["cameras"][prob["obs_camera"][0], 9:12]
+        over["lms"] = lms
+    elif case == "null_workspace":
+        ws = None
+    st, _keep = _problem(prob, **over)
+    h = C.c_void_p()
+    rc = B.lib.daba_create(C.byref(st), C.byref(opts), ws, 1 << 40, None, C.byref(h))
+    expect = -5 if case == "degenerate" else -1
+    assert rc == expect, (rc, B.lib.daba_last_error(None))
+    assert not h.value
+    assert len(B.lib.daba_last_error(None)) > 0
