@@ -140,7 +140,8 @@ int daba_get_metrics(daba_handle *h, double *metrics);
 
 /* Timing hook for measurement: runs n_iters iterations and returns, through
  * ms_out (host [3]), the summed GPU time in ms of the observation pass, the
- * entity solves followed by the restart test, and the selection, measured
+ * camera and landmark subproblems followed by the restart test, and the
+ * selection, measured
  * with HIP events on the handle's stream around each launch.  Synchronizes. */
 int daba_iterate_timed(daba_handle *h, int n_iters, double *ms_out);
 

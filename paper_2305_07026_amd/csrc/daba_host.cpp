@@ -558,6 +558,7 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         p.fp32 = fp32 ? 1 : 0;
         p.flags = opt->debug_flags;
         check_assumption2(prob);
+        // device work starts here
 
         hipStream_t s = h->stream;
         const int64_t K = L.K;
@@ -626,11 +627,18 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
     }
 }
 
-static void launch_iteration(const Params& p, int k, hipStream_t s) {
+// One iteration on stream s; ev (optional, 4 events) brackets the observation
+// pass, the entity solves with the restart test, and the selection.
+static void launch_iteration(daba_handle* h, int k, hipStream_t s, hipEvent_t* ev = nullptr) {
+    const Params& p = h->p;
+    if (ev) hipcheck(hipEventRecord(ev[0], s), "event");
     hipcheck(launch_obs_pass(p, k, s), "k_obs");
+    if (ev) hipcheck(hipEventRecord(ev[1], s), "event");
     hipcheck(launch_entity(p, k, s), "k_entity");
     hipcheck(launch_decide(p, k, s), "k_decide");
+    if (ev) hipcheck(hipEventRecord(ev[2], s), "event");
     hipcheck(launch_select(p, k, s), "k_select");
+    if (ev) hipcheck(hipEventRecord(ev[3], s), "event");
 }
 
 // Captures iterations with k mod 6 = 0..5 once; replaying the graph runs one
@@ -640,7 +648,7 @@ static bool ensure_period_graph(daba_handle* h) {
     if (!h->graphs) return false;
     hipcheck(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     hipcheck(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
-    for (int k = 0; k < 6; ++k) launch_iteration(h->p, k, h->cap_stream);
+    for (int k = 0; k < 6; ++k) launch_iteration(h, k, h->cap_stream);
     hipGraph_t g = nullptr;
     hipcheck(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
     hipError_t e = hipGraphInstantiate(&h->period, g, nullptr, nullptr, 0);
@@ -685,18 +693,8 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
                 continue;
             }
             const int k = (int)(h->k % 6);
-            hipEvent_t* e5 = ms ? &ev[4 * pooled] : nullptr;
-            if (ms) hipcheck(hipEventRecord(e5[0], s), "event");
-            hipcheck(launch_obs_pass(p, k, s), "k_obs");
-            if (ms) hipcheck(hipEventRecord(e5[1], s), "event");
-            hipcheck(launch_entity(p, k, s), "k_entity");
-            hipcheck(launch_decide(p, k, s), "k_decide");
-            if (ms) hipcheck(hipEventRecord(e5[2], s), "event");
-            hipcheck(launch_select(p, k, s), "k_select");
-            if (ms) {
-                hipcheck(hipEventRecord(e5[3], s), "event");
-                if (++pooled == kPool) drain();
-            }
+            launch_iteration(h, k, s, ms ? &ev[4 * pooled] : nullptr);
+            if (ms && ++pooled == kPool) drain();
             h->k++;
         }
         if (F_trace) {

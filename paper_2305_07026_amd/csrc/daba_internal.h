@@ -88,8 +88,8 @@ struct Params {
     double* lpair[2];
     float* lpair32[2];
     double* lcand[2];
-    double* rec;
-    float* rec32;
+    double* rec;              // [K * 8] landmark-side records at their slots
+    float* rec32;             // [K * 8] the same in FP32 (mixed precision)
     double* tile_vals;        // [T * kTileVals]
     double* tile_bins;        // [2S * T], column q*S + beta
     double* camblk_vals;      // [nCamBlocks * 4]
@@ -114,7 +114,7 @@ struct Params {
 // Launchers (daba_kernels.hip).  k mod 3 selects the camera generation and
 // k mod 2 the landmark pair buffer.
 hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s);
-hipError_t launch_entity(const Params& p, int k, hipStream_t s);
+hipError_t launch_entity(const Params& p, int k, hipStream_t s);  // camera and landmark subproblems
 hipError_t launch_decide(const Params& p, int k, hipStream_t s);
 hipError_t launch_select(const Params& p, int k, hipStream_t s);
 // Objective shares at (cams, lpair, uv): tile F shares and bins -> Fsh^a and F.

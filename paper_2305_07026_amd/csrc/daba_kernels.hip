@@ -10,8 +10,10 @@
 //              camera moments of both surrogates (FP64), the F share and the
 //              surrogate-gap share; bins the landmark-side shares per
 //              partition; writes the landmark-side record to its slot.
-//   k_entity   camera subproblems (Levenberg-Marquardt on the moments),
-//              landmark closed forms, column sums of the partition bins.
+//   k_entity   camera subproblems (Levenberg-Marquardt on the moments) and,
+//              in other blocks of the same launch, landmark subproblems (one
+//              lane per landmark: the records k_obs wrote at its slots, then
+//              the closed form) and the column sums of the partition bins.
 //   k_decide   per-partition restart metrics and test (eq. Fak, lFak, Eak).
 //   k_select   picks each partition's candidate, rolls the iterates and
 //              extrapolates the cameras for the next iteration.
@@ -30,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 namespace daba {
 
@@ -232,6 +235,19 @@ __device__ __forceinline__ void bin_add_sorted(double v0, double v1, int key, in
     }
 }
 
+// Adds a run's per-lane sums into bins[key] (no-op for key < 0) and clears them.
+__device__ __forceinline__ void flush_run(int key, double& r0, double& r1, int lane, double* bins0, double* bins1) {
+    if (key >= 0) {
+        const double s0 = wave_sum(r0), s1 = wave_sum(r1);
+        if (lane == 0) {
+            bins0[key] += s0;
+            bins1[key] += s1;
+        }
+    }
+    r0 = 0.0;
+    r1 = 0.0;
+}
+
 // ------------------------------------------------------- observation pass
 
 constexpr int kAcc = 78;   // 2 x 38 moments + F share + gap share
@@ -272,17 +288,23 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
     const R* __restrict__ pairs = pair_base<R>(p, k);
     R* __restrict__ rec = rec_base<R>(p);
     bool bad = false;
+    int run_key = -1;       // wave-uniform landmark partition of the open run
+    double run0 = 0.0, run1 = 0.0;
     __syncthreads();
 
+    int li_next = beg + lane < end ? p.obs_lm[beg + lane] : 0;
     for (int base = beg; base < end; base += kWave) {
         const int o = base + lane;
         const bool on = o < end;
+        // the next step's landmark index is requested before this step's
+        // gather, so each step waits for one memory round trip, not two
+        const int li = li_next;
+        li_next = o + kWave < end ? p.obs_lm[o + kWave] : 0;
         double hF = 0.0, gp = 0.0;
         int key = -1;
         if (on) {
             R ux, uy;
             load_uv<R>(p, o, ux, uy);
-            const int li = p.obs_lm[o];
             const int slot = p.obs_slot[o];
             const LmRead<R> L = read_pair(pairs, li);
             const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
@@ -292,6 +314,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
             eval_obs<LOSS, R>(ck, L.lk[0], L.lk[1], L.lk[2], ux, uy, r2u, r4u, delta, ek);
             bad |= !(ek.r2 > (R)1e-24);
             add_moments<R>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
+            // landmark-side record: W = w lambda^2 and V = w lambda e_w per surrogate
             R rv[8];
             rv[0] = ek.w * ek.lam * ek.lam;
             rv[1] = ek.w * ek.lam * ek.e[0];
@@ -334,16 +357,27 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
         acc[2 * kMom] += hF;
         acc[2 * kMom + 1] += gp;
         if (S > 1) {
-            bin_add_sorted(hF, -gp, key, lane, bins[wv][0], bins[wv][1]);
-        } else {
-            // one partition: the landmark side of every pair belongs to it
-            double s0 = wave_sum(hF), s1 = wave_sum(-gp);
-            if (lane == 0) {
-                bins[wv][0][0] += s0;
-                bins[wv][1][0] += s1;
+            // landmark-side shares by landmark partition.  Within a camera the
+            // observations are sorted by landmark partition, so most steps
+            // hold one partition: accumulate those per lane and reduce once
+            // per run; a step that straddles partitions uses a segmented sum.
+            const int k0 = uniform_int(key);
+            const bool uni = __all(!on || key == k0);
+            if (uni) {
+                if (k0 != run_key) {
+                    flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
+                    run_key = k0;
+                }
+                run0 += hF;
+                run1 -= gp;
+            } else {
+                flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
+                run_key = -1;
+                bin_add_sorted(hF, -gp, key, lane, bins[wv][0], bins[wv][1]);
             }
         }
     }
+    if (S > 1) flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
     if (bad) p.st->err = -5;
 
     // tile totals: LDS transpose, lane v sums value v over the 64 lanes
@@ -363,9 +397,17 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
         __syncthreads();
     }
     if (active) {
-        for (int b = lane; b < S; b += kWave) {
-            p.tile_bins[(size_t)b * p.T + t] = bins[wv][0][b];
-            p.tile_bins[(size_t)(S + b) * p.T + t] = bins[wv][1][b];
+        if (S == 1) {
+            // one partition: the landmark side of every pair belongs to it
+            if (lane == 0) {
+                p.tile_bins[t] = p.tile_vals[(size_t)t * kTileVals + 2 * kMom];
+                p.tile_bins[(size_t)p.T + t] = -p.tile_vals[(size_t)t * kTileVals + 2 * kMom + 1];
+            }
+        } else {
+            for (int b = lane; b < S; b += kWave) {
+                p.tile_bins[(size_t)b * p.T + t] = bins[wv][0][b];
+                p.tile_bins[(size_t)(S + b) * p.T + t] = bins[wv][1][b];
+            }
         }
     }
 }
@@ -793,11 +835,11 @@ __device__ void nearest_rotation(const double* M, double* R) {
 
 // ------------------------------------------------------- restart decision
 
-// One block, after k_entity: per-partition restart metrics and test, the
-// objective trace and the Nesterov scalars.  (A separate launch: a
-// last-block-done decision inside k_entity needs a device-scope release fence
-// in every block, which writes back the whole L2 of each XCD and costs more
-// than the launch.)
+// One block, after k_entity: per-partition restart metrics and test,
+// the objective trace and the Nesterov scalars.  (A separate launch: a
+// last-block-done decision inside the entity kernels needs a device-scope
+// release fence in every block, which writes back the whole L2 of each XCD
+// and costs more than the launch.)
 __global__ __launch_bounds__(256) void k_decide(Params p, int k) {
     __shared__ double sFsh[kMaxPart];
     const int lane = threadIdx.x & (kWave - 1);
@@ -860,165 +902,119 @@ __global__ __launch_bounds__(256) void k_decide(Params p, int k) {
 }
 
 
+// Camera subproblems of one block of <= 128 cameras in one partition:
+// threads [0,128) solve the plain surrogate, [128,256) the accelerated one.
 template <bool ACC>
-__global__ __launch_bounds__(256) void k_entity(Params p, int k) {
-    __shared__ double sred[4][8];
+__device__ __forceinline__ void camera_role(const Params& p, int k, int b, double (*sred)[4]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
-    const int b = blockIdx.x;
     const double xi = p.xi;
-
-    if (b < p.nCamBlocks) {
-        // ---- camera subproblems: threads [0,128) plain MM, [128,256) accelerated
-        const int surr = threadIdx.x / kCamBlock;
-        const int ci = p.camblock_c0[b] + (threadIdx.x % kCamBlock);
-        double dv = 0.0, f1 = 0.0, f2 = 0.0;
-        if (ci < p.camblock_c1[b] && (surr == 0 || ACC)) {
-            double mom[kMom];
+    const int surr = threadIdx.x / kCamBlock;
+    const int ci = p.camblock_c0[b] + (threadIdx.x % kCamBlock);
+    double dv = 0.0, f1 = 0.0, f2 = 0.0;
+    if (ci < p.camblock_c1[b] && (surr == 0 || ACC)) {
+        double mom[kMom];
+#pragma unroll
+        for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
+        const int t0 = p.cam_tile_off[ci], t1 = p.cam_tile_off[ci + 1];
+        const int off = surr == 0 ? 0 : kMom;
+        for (int t = t0; t < t1; ++t) {
+            const double* tv = p.tile_vals + (size_t)t * kTileVals;
+#pragma unroll
+            for (int a = 0; a < kMom; ++a) mom[a] += tv[off + a];
+            f1 += tv[2 * kMom];
+            f2 += tv[2 * kMom + 1];
+        }
+        const CamD ck = load_camd(p.cams[k % 3] + (size_t)ci * kCamRec);
+        const CamD y = surr == 0 ? ck : load_camd(p.cam_bar + (size_t)ci * kCamRec);
+        const CamD c = lm_camera(mom, y, xi, p.inner_steps);
+        store_camd(p.cam_cand[surr] + (size_t)ci * kCamRec, c);
+        if (surr == 1) {
+            // the plain surrogate (about x^k) at the accelerated candidate
 #pragma unroll
             for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
-            const int t0 = p.cam_tile_off[ci], t1 = p.cam_tile_off[ci + 1];
-            const int off = surr == 0 ? 0 : kMom;
             for (int t = t0; t < t1; ++t) {
                 const double* tv = p.tile_vals + (size_t)t * kTileVals;
 #pragma unroll
-                for (int a = 0; a < kMom; ++a) mom[a] += tv[off + a];
-                f1 += tv[2 * kMom];
-                f2 += tv[2 * kMom + 1];
+                for (int a = 0; a < kMom; ++a) mom[a] += tv[a];
             }
-            const CamD ck = load_camd(p.cams[k % 3] + (size_t)ci * kCamRec);
-            const CamD y = surr == 0 ? ck : load_camd(p.cam_bar + (size_t)ci * kCamRec);
-            const CamD c = lm_camera(mom, y, xi, p.inner_steps);
-            store_camd(p.cam_cand[surr] + (size_t)ci * kCamRec, c);
-            if (surr == 1) {
-                // the plain surrogate (about x^k) at the accelerated candidate
+        }
+        dv = phi_delta(mom, ck, c, xi);
+        if (surr == 1) f1 = f2 = 0.0;
+    }
+    // block sums in a fixed order: (dmm, dacc, F share, gap share)
+    double v0 = surr == 0 ? dv : 0.0, v1 = surr == 1 ? dv : 0.0;
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    f1 = wave_sum(f1);
+    f2 = wave_sum(f2);
+    if (lane == 0) {
+        sred[wv][0] = v0;
+        sred[wv][1] = v1;
+        sred[wv][2] = f1;
+        sred[wv][3] = f2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
+        p.camblk_vals[(size_t)b * 4 + threadIdx.x] = s;
+    }
+}
+
+// Sums a landmark's records (slots base + q n + lane, q < D), four in flight
+// per lane; FP32 records are accumulated in FP64.
+template <typename RT, bool ACC>
+__device__ __forceinline__ void sum_records(const RT* __restrict__ rec, int64_t base, int n, int lane, int D,
+                                            double& W0, double* V0, double& W1, double* V1) {
+    using V4 = typename std::conditional<std::is_same<RT, double>::value, double4, float4>::type;
+    constexpr int U = 4;
+    for (int q0 = 0; q0 < D; q0 += U) {
+        V4 ra[U], rb[U];
 #pragma unroll
-                for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
-                for (int t = t0; t < t1; ++t) {
-                    const double* tv = p.tile_vals + (size_t)t * kTileVals;
-#pragma unroll
-                    for (int a = 0; a < kMom; ++a) mom[a] += tv[a];
-                }
+        for (int u = 0; u < U; ++u) {
+            if (q0 + u < D) {
+                const V4* r = reinterpret_cast<const V4*>(rec + (size_t)(base + (int64_t)(q0 + u) * n + lane) * 8);
+                ra[u] = r[0];
+                if (ACC) rb[u] = r[1];
             }
-            dv = phi_delta(mom, ck, c, xi);
-            if (surr == 1) f1 = f2 = 0.0;
         }
-        // block sums in a fixed order: (dmm, dacc, F share, gap share)
-        double v0 = surr == 0 ? dv : 0.0, v1 = surr == 1 ? dv : 0.0;
-        v0 = wave_sum(v0);
-        v1 = wave_sum(v1);
-        f1 = wave_sum(f1);
-        f2 = wave_sum(f2);
-        if (lane == 0) {
-            sred[wv][0] = v0;
-            sred[wv][1] = v1;
-            sred[wv][2] = f1;
-            sred[wv][3] = f2;
-        }
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            double s = 0.0;
-            for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
-            p.camblk_vals[(size_t)b * 4 + threadIdx.x] = s;
-        }
-    } else if (b - p.nCamBlocks < p.nLmBlocks) {
-        const int lb = b - p.nCamBlocks;
-        // ---- landmark subproblems: one wave per group of equal track length
-        const int g = p.lmblock_g0[lb] + wv;
-        double dmm = 0.0, dacc = 0.0;
-        if (g < p.lmblock_g1[lb]) {
-            const int n = p.group_n[g], D = p.group_deg[g];
-            const int li = p.group_lm0[g] + lane;
-            const int64_t base = p.group_base[g];
-            if (lane < n) {
-                double W0 = 0, V0[3] = {0, 0, 0}, W1 = 0, V1[3] = {0, 0, 0};
-                // eight records in flight per lane before they are summed
-                constexpr int U = 8;
-                for (int q0 = 0; q0 < D; q0 += U) {
-                    if (p.fp32) {
-                        float4 ra[U], rb[U];
 #pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            if (q0 + u < D) {
-                                const float4* r = reinterpret_cast<const float4*>(
-                                    p.rec32 + (size_t)(base + (int64_t)(q0 + u) * n + lane) * 8);
-                                ra[u] = r[0];
-                                if (ACC) rb[u] = r[1];
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            if (q0 + u < D) {
-                                W0 += ra[u].x; V0[0] += ra[u].y; V0[1] += ra[u].z; V0[2] += ra[u].w;
-                                if (ACC) { W1 += rb[u].x; V1[0] += rb[u].y; V1[1] += rb[u].z; V1[2] += rb[u].w; }
-                            }
-                        }
-                    } else {
-                        double4 ra[U], rb[U];
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            if (q0 + u < D) {
-                                const double4* r = reinterpret_cast<const double4*>(
-                                    p.rec + (size_t)(base + (int64_t)(q0 + u) * n + lane) * 8);
-                                ra[u] = r[0];
-                                if (ACC) rb[u] = r[1];
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            if (q0 + u < D) {
-                                W0 += ra[u].x; V0[0] += ra[u].y; V0[1] += ra[u].z; V0[2] += ra[u].w;
-                                if (ACC) { W1 += rb[u].x; V1[0] += rb[u].y; V1[1] += rb[u].z; V1[2] += rb[u].w; }
-                            }
-                        }
-                    }
-                }
-                const LmRead<double> L = read_pair(p.lpair[k & 1], li);
-                double dl[3], nm = 0.0, dv = 0.0;
-                const double den0 = 2.0 * W0 + xi;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    dl[a] = V0[a] / den0;
-                    nm += dl[a] * dl[a];
-                    dv += dl[a] * V0[a];
-                }
-                dmm = (W0 + 0.5 * xi) * nm - dv;
-                double* cm = p.lcand[0] + (size_t)li * 4;
-                cm[0] = L.lk[0] + dl[0];
-                cm[1] = L.lk[1] + dl[1];
-                cm[2] = L.lk[2] + dl[2];
+        for (int u = 0; u < U; ++u) {
+            if (q0 + u < D) {
+                W0 += ra[u].x;
+                V0[0] += ra[u].y;
+                V0[1] += ra[u].z;
+                V0[2] += ra[u].w;
                 if (ACC) {
-                    const double gam = p.st->gamma;
-                    const double den1 = 2.0 * W1 + xi;
-                    double da[3], na = 0.0, va = 0.0;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
-                        double la = lbar + V1[a] / den1;
-                        p.lcand[1][(size_t)li * 4 + a] = la;
-                        da[a] = la - L.lk[a];
-                        na += da[a] * da[a];
-                        va += da[a] * V0[a];
-                    }
-                    dacc = (W0 + 0.5 * xi) * na - va;
+                    W1 += rb[u].x;
+                    V1[0] += rb[u].y;
+                    V1[1] += rb[u].z;
+                    V1[2] += rb[u].w;
                 }
             }
         }
-        dmm = wave_sum(dmm);
-        dacc = wave_sum(dacc);
-        if (lane == 0) {
-            sred[wv][0] = dmm;
-            sred[wv][1] = dacc;
-        }
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            double s = 0.0;
-            for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
-            p.lmblk_vals[(size_t)lb * 2 + threadIdx.x] = s;
-        }
-    } else {
-        // ---- column sums of the per-tile partition bins
-        const int col = b - p.nCamBlocks - p.nLmBlocks;
+    }
+}
+
+// One launch, three kinds of blocks: camera subproblems, landmark subproblems
+// (one wave per group of landmarks with equal track length), and column sums
+// of the per-tile partition bins.  The roles are independent, so the camera
+// solves (long serial chains on few threads) overlap the landmark pass.
+template <typename RT, bool ACC>
+__global__ __launch_bounds__(256) void k_entity(Params p, int k) {
+    __shared__ double sred[4][4];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const double xi = p.xi;
+    if ((int)blockIdx.x < p.nCamBlocks) {
+        camera_role<ACC>(p, k, blockIdx.x, sred);
+        return;
+    }
+    const int lb = blockIdx.x - p.nCamBlocks;
+    if (lb >= p.nLmBlocks) {
+        // column sums of the per-tile partition bins
+        const int col = lb - p.nLmBlocks;
         const double* src = p.tile_bins + (size_t)col * p.T;
         double s = 0.0;
         for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
@@ -1026,6 +1022,60 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
         if (lane == 0) sred[wv][0] = s;
         __syncthreads();
         if (threadIdx.x == 0) p.colsum[col] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+        return;
+    }
+    // ---- landmark subproblems: one wave per group of equal track length
+    const int g = p.lmblock_g0[lb] + wv;
+    double dmm = 0.0, dacc = 0.0;
+    if (g < p.lmblock_g1[lb]) {
+        const int n = p.group_n[g], D = p.group_deg[g];
+        const int li = p.group_lm0[g] + lane;
+        const int64_t base = p.group_base[g];
+        if (lane < n) {
+            double W0 = 0, V0[3] = {0, 0, 0}, W1 = 0, V1[3] = {0, 0, 0};
+            sum_records<RT, ACC>(rec_base<RT>(p), base, n, lane, D, W0, V0, W1, V1);
+            const LmRead<double> L = read_pair(p.lpair[k & 1], li);
+            double dl[3], nm = 0.0, dv = 0.0;
+            const double den0 = 2.0 * W0 + xi;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dl[a] = V0[a] / den0;
+                nm += dl[a] * dl[a];
+                dv += dl[a] * V0[a];
+            }
+            dmm = (W0 + 0.5 * xi) * nm - dv;
+            double* cm = p.lcand[0] + (size_t)li * 4;
+            cm[0] = L.lk[0] + dl[0];
+            cm[1] = L.lk[1] + dl[1];
+            cm[2] = L.lk[2] + dl[2];
+            if (ACC) {
+                const double gam = p.st->gamma;
+                const double den1 = 2.0 * W1 + xi;
+                double da[3], na = 0.0, va = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
+                    double la = lbar + V1[a] / den1;
+                    p.lcand[1][(size_t)li * 4 + a] = la;
+                    da[a] = la - L.lk[a];
+                    na += da[a] * da[a];
+                    va += da[a] * V0[a];
+                }
+                dacc = (W0 + 0.5 * xi) * na - va;
+            }
+        }
+    }
+    dmm = wave_sum(dmm);
+    dacc = wave_sum(dacc);
+    if (lane == 0) {
+        sred[wv][0] = dmm;
+        sred[wv][1] = dacc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
+        p.lmblk_vals[(size_t)lb * 2 + threadIdx.x] = s;
     }
 }
 
@@ -1364,8 +1414,13 @@ hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s) {
 
 hipError_t launch_entity(const Params& p, int k, hipStream_t s) {
     dim3 grid(p.nCamBlocks + p.nLmBlocks + 2 * p.S), block(256);
-    if (p.accelerate) hipLaunchKernelGGL((k_entity<true>), grid, block, 0, s, p, k);
-    else hipLaunchKernelGGL((k_entity<false>), grid, block, 0, s, p, k);
+    if (p.fp32) {
+        if (p.accelerate) hipLaunchKernelGGL((k_entity<float, true>), grid, block, 0, s, p, k);
+        else hipLaunchKernelGGL((k_entity<float, false>), grid, block, 0, s, p, k);
+    } else {
+        if (p.accelerate) hipLaunchKernelGGL((k_entity<double, true>), grid, block, 0, s, p, k);
+        else hipLaunchKernelGGL((k_entity<double, false>), grid, block, 0, s, p, k);
+    }
     return hipGetLastError();
 }
 
