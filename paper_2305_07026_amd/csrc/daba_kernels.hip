@@ -110,6 +110,33 @@ __device__ __forceinline__ void eval_obs(const CamT<R>& c, R l0, R l1, R l2, R u
     o.rho = loss_rho<LOSS, R>(o.s, delta, o.w);
 }
 
+// eq. error written out in the camera frame for any 3x3 R (the form the
+// objective and its gradient are defined on): n = R^T (l - t),
+// lambda = n . p / |l - t|^2, e = p - lambda n.  On SO(3) it equals R^T e_w.
+template <int LOSS, typename R>
+struct ObsEvalCF {
+    R p[3], m[3], n[3], lam, e[3], s, w, rho, r2;
+};
+
+template <int LOSS, typename R>
+__device__ __forceinline__ void eval_obs_cf(const CamT<R>& c, R l0, R l1, R l2, R ux, R uy, R r2u, R r4u,
+                                            R delta, ObsEvalCF<LOSS, R>& o) {
+    o.p[0] = ux;
+    o.p[1] = uy;
+    o.p[2] = c.d[0] + c.d[1] * r2u + c.d[2] * r4u;
+    o.m[0] = l0 - c.t[0];
+    o.m[1] = l1 - c.t[1];
+    o.m[2] = l2 - c.t[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.n[a] = c.r[a] * o.m[0] + c.r[3 + a] * o.m[1] + c.r[6 + a] * o.m[2];
+    o.r2 = o.m[0] * o.m[0] + o.m[1] * o.m[1] + o.m[2] * o.m[2];
+    o.lam = (o.n[0] * o.p[0] + o.n[1] * o.p[1] + o.n[2] * o.p[2]) / o.r2;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.e[a] = o.p[a] - o.lam * o.n[a];
+    o.s = o.e[0] * o.e[0] + o.e[1] * o.e[1] + o.e[2] * o.e[2];
+    o.rho = loss_rho<LOSS, R>(o.s, delta, o.w);
+}
+
 // Moments of one surrogate (see header comment): a[0..19] = Z, a[20..37] = Y.
 template <typename R>
 __device__ __forceinline__ void add_moments(double* a, R w, R lam, R ux, R uy, R r2, R r4, R r6, R r8,
@@ -1178,8 +1205,8 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_objective(Params p, const 
             const R ux = (R)u2.x, uy = (R)u2.y;
             const LmRead<double> L = read_pair(lpair, p.obs_lm[o]);
             const R r2u = ux * ux + uy * uy;
-            ObsEval<LOSS, R> e;
-            eval_obs<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
+            ObsEvalCF<LOSS, R> e;
+            eval_obs_cf<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
             bad |= !(e.r2 > (R)1e-24);
             hF = (double)((R)0.25 * e.rho);
             key = L.beta;
@@ -1304,26 +1331,33 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_grad_obs(Params p, const d
             const R ux = (R)u2.x, uy = (R)u2.y;
             const LmRead<double> L = read_pair(lpair, p.obs_lm[o]);
             const R r2u = ux * ux + uy * uy;
-            ObsEval<LOSS, R> e;
-            eval_obs<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
-            // camera-frame residual ec = R^T e_w
-            R ec[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) ec[a] = c.r[a] * e.e[0] + c.r[3 + a] * e.e[1] + c.r[6 + a] * e.e[2];
+            ObsEvalCF<LOSS, R> e;
+            eval_obs_cf<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
+            const R* ec = e.e;
             const R wl = e.w * e.lam;
+            // grad_R = -w (m m^T / |m|^2) R (e p^T + p e^T)
+            //        = -(w / |m|^2) m ((n . e) p^T + (n . p) e^T), exact for any 3x3 R
+            const R ne = e.n[0] * ec[0] + e.n[1] * ec[1] + e.n[2] * ec[2];
+            const R np = e.lam * e.r2;
+            const R wr = e.w / e.r2;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int bb = 0; bb < 3; ++bb) acc[3 * a + bb] += (double)(-wl * e.m[a] * ec[bb]);
+                for (int bb = 0; bb < 3; ++bb)
+                    acc[3 * a + bb] += (double)(-wr * e.m[a] * (ne * e.p[bb] + np * ec[bb]));
+            // grad_t = w lambda R e,  grad_l = -w lambda R e
+            R Re[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) acc[9 + a] += (double)(wl * e.e[a]);
+            for (int a = 0; a < 3; ++a) Re[a] = c.r[3 * a] * ec[0] + c.r[3 * a + 1] * ec[1] + c.r[3 * a + 2] * ec[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[9 + a] += (double)(wl * Re[a]);
             acc[12] += (double)(e.w * ec[2]);
             acc[13] += (double)(e.w * ec[2] * r2u);
             acc[14] += (double)(e.w * ec[2] * r2u * r2u);
             double* lr = p.rec + (size_t)p.obs_slot[o] * 8;
-            lr[0] = (double)(-wl * e.e[0]);
-            lr[1] = (double)(-wl * e.e[1]);
-            lr[2] = (double)(-wl * e.e[2]);
+            lr[0] = (double)(-wl * Re[0]);
+            lr[1] = (double)(-wl * Re[1]);
+            lr[2] = (double)(-wl * Re[2]);
             if (g_uv) {
                 const R dz = (R)2 * c.d[1] + (R)4 * c.d[2] * r2u;
                 const int oi = p.obs_orig[o];
