@@ -282,13 +282,12 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.camblk_vals = c.take<double>(L.camblock_c0.size() * 4);
     p.lmblk_vals = c.take<double>(L.lmblock_g0.size() * 2);
     p.colsum = c.take<double>(2 * S);
-    p.Fbar = c.take<double>(S);
-    p.E = c.take<double>(S);
-    p.EE = c.take<double>(S);
-    p.Fprev = c.take<double>(S);
-    p.restart = c.take<int>(S);
+    p.Fbar = c.take<double>(2 * S);
+    p.E = c.take<double>(2 * S);
+    p.EE = c.take<double>(2 * S);
+    p.Fprev = c.take<double>(2 * S);
     p.metrics = c.take<double>(4 * S);
-    p.st = c.take<DevState>(1);
+    p.st = c.take<DevState>(2);
     p.trace = c.take<double>(kTraceCap);
     p.trace_cap = kTraceCap;
     p.tmp_cams = c.take<double>(M * kCamRec);
@@ -479,10 +478,11 @@ void init_metrics(daba_handle* h) {
     download(part.data(), h->d_obj, part.size() * sizeof(double), h->stream);
     sync_and_check(h);
     const int S = h->L.S;
-    upload(p.Fbar, part.data(), S * sizeof(double), h->stream);
-    upload(p.E, part.data(), S * sizeof(double), h->stream);
-    upload(p.EE, part.data(), S * sizeof(double), h->stream);
-    upload(p.Fprev, part.data(), S * sizeof(double), h->stream);
+    const size_t slot = (size_t)(h->k & 1) * S;
+    upload(p.Fbar + slot, part.data(), S * sizeof(double), h->stream);
+    upload(p.E + slot, part.data(), S * sizeof(double), h->stream);
+    upload(p.EE + slot, part.data(), S * sizeof(double), h->stream);
+    upload(p.Fprev + slot, part.data(), S * sizeof(double), h->stream);
     hipcheck(hipStreamSynchronize(h->stream), "sync");
 }
 
@@ -602,11 +602,11 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         upload((void*)p.lm_ext, L.lm_ext.data(), L.N * sizeof(int), s);
         hipcheck(hipStreamSynchronize(s), "sync");
         // state: x^(-1) = x^(0), s = 1, gamma = 0
-        DevState st{};
-        st.s = 1.0;
-        st.gamma = 0.0;
-        st.k = 0;
-        upload(p.st, &st, sizeof st, s);
+        DevState st[2]{};
+        st[0].s = 1.0;
+        st[0].gamma = 0.0;
+        st[0].k = 0;
+        upload(p.st, st, sizeof st, s);
         std::vector<double> zero(std::max<int64_t>(4 * L.S, 1), 0.0);
         upload(p.metrics, zero.data(), 4 * L.S * sizeof(double), s);
         hipcheck(hipStreamSynchronize(s), "sync");
@@ -628,16 +628,15 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
 }
 
 // One iteration on stream s; ev (optional, 4 events) brackets the observation
-// pass, the entity solves with the restart test, and the selection.
+// pass, the entity solves, and the restart test with the selection.
 static void launch_iteration(daba_handle* h, int k, hipStream_t s, hipEvent_t* ev = nullptr) {
     const Params& p = h->p;
     if (ev) hipcheck(hipEventRecord(ev[0], s), "event");
     hipcheck(launch_obs_pass(p, k, s), "k_obs");
     if (ev) hipcheck(hipEventRecord(ev[1], s), "event");
     hipcheck(launch_entity(p, k, s), "k_entity");
-    hipcheck(launch_decide(p, k, s), "k_decide");
     if (ev) hipcheck(hipEventRecord(ev[2], s), "event");
-    hipcheck(launch_select(p, k, s), "k_select");
+    hipcheck(launch_decide_select(p, k, s), "k_decide_select");
     if (ev) hipcheck(hipEventRecord(ev[3], s), "event");
 }
 
@@ -837,10 +836,11 @@ int daba_get_state(daba_handle* h, double* cams, double* lms, double* cams_prev,
         if (cc->p4) {
             const int S = L.S;
             std::vector<double> a(S), b(S), c2(S), d(S);
-            download(a.data(), p.Fbar, S * sizeof(double), s);
-            download(b.data(), p.E, S * sizeof(double), s);
-            download(c2.data(), p.EE, S * sizeof(double), s);
-            download(d.data(), p.Fprev, S * sizeof(double), s);
+            const size_t slot = (size_t)(k & 1) * S;
+            download(a.data(), p.Fbar + slot, S * sizeof(double), s);
+            download(b.data(), p.E + slot, S * sizeof(double), s);
+            download(c2.data(), p.EE + slot, S * sizeof(double), s);
+            download(d.data(), p.Fprev + slot, S * sizeof(double), s);
             hipcheck(hipStreamSynchronize(s), "sync");
             for (int q = 0; q < S; ++q) {
                 cc->p4[4 * q] = s2 * a[q];
@@ -851,7 +851,7 @@ int daba_get_state(daba_handle* h, double* cams, double* lms, double* cams_prev,
         }
         if (cc->sc) {
             DevState st;
-            download(&st, p.st, sizeof st, s);
+            download(&st, p.st + (k & 1), sizeof st, s);
             hipcheck(hipStreamSynchronize(s), "sync");
             cc->sc[0] = st.s;
             cc->sc[1] = (double)st.k;
@@ -870,10 +870,11 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
         hipStream_t s = hh->stream;
         hipcheck(hipStreamSynchronize(s), "sync");
         if (cc->sc) {
-            DevState st;
-            download(&st, p.st, sizeof st, s);
+            DevState sts[2];
+            download(sts, p.st, sizeof sts, s);
             hipcheck(hipStreamSynchronize(s), "sync");
             if (!(cc->sc[0] >= 1.0) || cc->sc[1] < 0) fail(DABA_E_INVAL, "bad scalars (s >= 1, k >= 0)");
+            DevState st = sts[((int64_t)cc->sc[1]) & 1];
             st.s = cc->sc[0];
             const double s1 = (std::sqrt(4.0 * st.s * st.s + 1.0) + 1.0) / 2.0;
             st.gamma = p.accelerate ? (st.s - 1.0) / s1 : 0.0;
@@ -891,6 +892,13 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
                 upload(p.cams[kn % 3], c0.data(), c0.size() * sizeof(double), s);
                 upload(p.cams[(kn + 2) % 3], c1.data(), c1.size() * sizeof(double), s);
                 upload(p.lpair[kn & 1], pr.data(), pr.size() * sizeof(double), s);
+                if ((kn & 1) != (ko & 1)) {
+                    // the restart bookkeeping follows the counter's parity slot
+                    const int S = L.S;
+                    for (double* arr : {p.Fbar, p.E, p.EE, p.Fprev})
+                        hipcheck(hipMemcpyAsync(arr + (size_t)(kn & 1) * S, arr + (size_t)(ko & 1) * S,
+                                                S * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+                }
                 if (p.fp32) {
                     std::vector<float> pf(L.N * kLmPair);
                     download(pf.data(), p.lpair32[ko & 1], pf.size() * sizeof(float), s);
@@ -901,7 +909,7 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
             }
             hh->k = knew;
             st.k = knew;
-            upload(p.st, &st, sizeof st, s);
+            upload(p.st + (knew & 1), &st, sizeof st, s);
             hipcheck(hipStreamSynchronize(s), "sync");
         }
         write_point(hh, cc->c, cc->l, cc->cp, cc->lp);
@@ -915,10 +923,11 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
                 c2[q] = cc->p4[4 * q + 2] / s2;
                 d[q] = cc->p4[4 * q + 3] / s2;
             }
-            upload(p.Fbar, a.data(), S * sizeof(double), s);
-            upload(p.E, b.data(), S * sizeof(double), s);
-            upload(p.EE, c2.data(), S * sizeof(double), s);
-            upload(p.Fprev, d.data(), S * sizeof(double), s);
+            const size_t slot = (size_t)(hh->k & 1) * S;
+            upload(p.Fbar + slot, a.data(), S * sizeof(double), s);
+            upload(p.E + slot, b.data(), S * sizeof(double), s);
+            upload(p.EE + slot, c2.data(), S * sizeof(double), s);
+            upload(p.Fprev + slot, d.data(), S * sizeof(double), s);
         }
         hipcheck(launch_extrapolate_cams(p, (int)(hh->k % 6), s), "extrapolate");
         hipcheck(hipStreamSynchronize(s), "sync");

@@ -33,12 +33,14 @@ constexpr int kCamBlock = 128;       // cameras per block of the camera solve
 constexpr int kLmWaves = 4;          // groups per block of the landmark pass
 constexpr int kMaxPart = 64;
 
+// Two slots, by iteration parity: iteration k reads slot k & 1 and writes
+// slot (k + 1) & 1.  The sticky error code lives in slot 0.
 struct DevState {
     double s;        // s^(k)
-    double gamma;    // gamma^(k) used by the current iteration
-    double F;        // F(x^k) of the last iteration (internal units)
+    double gamma;    // gamma^(k) used by iteration k
+    double F;        // F(x^(k-1)) computed by iteration k - 1 (internal units)
     int64_t k;
-    int32_t err;     // sticky error code (0 = none)
+    int32_t err;     // sticky error code (0 = none), slot 0 only
     int32_t pad;
 };
 
@@ -95,13 +97,14 @@ struct Params {
     double* camblk_vals;      // [nCamBlocks * 4]
     double* lmblk_vals;       // [nLmBlocks * 2]
     double* colsum;           // [2S]
-    double* Fbar;             // [S] Fbar^a(k-1) -> Fbar^a(k)
-    double* E;                // [S] E^a(k) -> E^a(k+1)
-    double* EE;               // [S] E^a(x^k | x^(k-1))
-    double* Fprev;            // [S] F^a(k-1)
-    int* restart;             // [S]
-    double* metrics;          // [S*4]
-    DevState* st;
+    // restart bookkeeping, [2 * S]: slot k & 1 holds the values iteration k
+    // starts from, slot (k + 1) & 1 receives the updated ones
+    double* Fbar;             // Fbar^a(k-1)
+    double* E;                // E^a(k)
+    double* EE;               // E^a(x^k | x^(k-1))
+    double* Fprev;            // F^a(k-1)
+    double* metrics;          // [S*4] of the last iteration
+    DevState* st;             // [2]
     double* trace;            // [trace_cap]
     int trace_cap;
     // scratch for caller-supplied points (objective / gradient)
@@ -115,8 +118,8 @@ struct Params {
 // k mod 2 the landmark pair buffer.
 hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s);
 hipError_t launch_entity(const Params& p, int k, hipStream_t s);  // camera and landmark subproblems
-hipError_t launch_decide(const Params& p, int k, hipStream_t s);
-hipError_t launch_select(const Params& p, int k, hipStream_t s);
+// Restart decision and selection (rolls x^k -> x^(k+1), extrapolates cameras).
+hipError_t launch_decide_select(const Params& p, int k, hipStream_t s);
 // Objective shares at (cams, lpair, uv): tile F shares and bins -> Fsh^a and F.
 hipError_t launch_objective(const Params& p, const double* cams, const double* lpair, const double2* uv,
                             double* part_out /*[S]*/, double* F_out /*[1]*/, hipStream_t s);

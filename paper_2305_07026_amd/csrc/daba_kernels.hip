@@ -14,9 +14,11 @@
 //              in other blocks of the same launch, landmark subproblems (one
 //              lane per landmark: the records k_obs wrote at its slots, then
 //              the closed form) and the column sums of the partition bins.
-//   k_decide   per-partition restart metrics and test (eq. Fak, lFak, Eak).
-//   k_select   picks each partition's candidate, rolls the iterates and
-//              extrapolates the cameras for the next iteration.
+//   k_decide_select
+//              per-partition restart metrics and test (eq. Fak, lFak, Eak),
+//              computed in every block; then picks each partition's
+//              candidate, rolls the iterates and extrapolates the cameras for
+//              the next iteration.
 //
 // Numerics.  Camera statistics are taken about the linearization point y
 // (Appendix-style moment form): with z = (ux, uy, 1, |u|^2, |u|^4, lambda),
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
     const CamT<R> cp = load_cam<R>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
     CamT<R> cb;
     if constexpr (ACC) cb = load_cam<R>(p.cam_bar + (size_t)ci * kCamRec);
-    const R gam = ACC ? (R)p.st->gamma : (R)0;
+    const R gam = ACC ? (R)p.st[k & 1].gamma : (R)0;
     const R delta = (R)p.delta;
     const R* __restrict__ pairs = pair_base<R>(p, k);
     R* __restrict__ rec = rec_base<R>(p);
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
         }
     }
     if (S > 1) flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
-    if (bad) p.st->err = -5;
+    if (bad) p.st[0].err = -5;
 
     // tile totals: LDS transpose, lane v sums value v over the 64 lanes
     double* rw = red[wv];
@@ -434,6 +436,278 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
             for (int b = lane; b < S; b += kWave) {
                 p.tile_bins[(size_t)b * p.T + t] = bins[wv][0][b];
                 p.tile_bins[(size_t)(S + b) * p.T + t] = bins[wv][1][b];
+            }
+        }
+    }
+}
+
+// ------------------------------------------- observation pass, FP64 form
+// The same pass with its memory traffic restructured for gfx950:
+//  * a step's 64 landmark pair records are fetched straight into LDS
+//    (global_load_lds, no VGPRs), four lanes per 64-byte record so that each
+//    wave instruction touches 16 cache lines instead of 64; pixels and slots
+//    come the same way.  The fetch for step s + 1 is issued while step s
+//    computes, into the other of two buffers, and the landmark indices it
+//    needs are loaded one step earlier still;
+//  * the landmark-side records of step s are staged in LDS and written at
+//    the start of step s + 1, again four lanes per record.  On this target
+//    a load's wait also waits for every store issued before it, so stores go
+//    out right after a step's wait, a whole step ahead of the next one.
+// Every wave waits for all of its vector memory operations at the start of
+// a step, explicitly: the compiler does not order an LDS read after an LDS
+// DMA into the same object.  The two buffers are separate objects, so that
+// reading one while the other is being filled needs no wait.
+struct ObsBuf {
+    double pair[kWave * kLmPair];  // pair records of a step, in observation order
+    double2 uv[kWave];
+    int slot[kWave];
+};
+constexpr int kRedHalf = 7;  // rows of the reduction transpose per buffer (7 x 65 <= 512)
+static_assert(kRedHalf * (kWave + 1) <= kWave * kLmPair, "reduction fits a pair buffer");
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+__device__ __forceinline__ void dma16(const void* g, void* l) {
+    __builtin_amdgcn_global_load_lds(g, (lds_ptr)l, 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const void* g, void* l) {
+    __builtin_amdgcn_global_load_lds(g, (lds_ptr)l, 4, 0, 0);
+}
+// vmcnt(0) with expcnt and lgkmcnt left alone (gfx9 encoding); the builtin
+// keeps the compiler's own wait bookkeeping informed, the empty asm keeps
+// memory accesses from moving across it
+__device__ __forceinline__ void wait_vmem() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// One wave per workgroup (one tile each): every LDS address is then a
+// compile-time offset from the lane's own, which keeps VGPRs for the 78
+// FP64 accumulators.
+template <int LOSS, bool ACC>
+__global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
+    __shared__ ObsBuf A;
+    __shared__ ObsBuf B;
+    __shared__ double stg[kWave * 8];  // landmark-side records of a step
+    __shared__ double bins[2][kMaxPart];
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x;
+    const bool active = t < p.T;
+    const int S = p.S;
+
+    for (int b = lane; b < S; b += kWave) {
+        bins[0][b] = 0.0;
+        bins[1][b] = 0.0;
+    }
+
+    double acc[kAcc];
+#pragma unroll
+    for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
+
+    int beg = 0, end = 0, ci = 0, alpha = 0;
+    if (active) {
+        ci = uniform_int(p.tile_cam[t]);
+        beg = uniform_int(p.tile_begin[t]);
+        end = uniform_int(p.tile_end[t]);
+        alpha = uniform_int(p.cam_part[ci]);
+    }
+    const CamT<double> ck = load_cam<double>(p.cams[k % 3] + (size_t)ci * kCamRec);
+    const CamT<double> cp = load_cam<double>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
+    CamT<double> cb;
+    if constexpr (ACC) cb = load_cam<double>(p.cam_bar + (size_t)ci * kCamRec);
+    const double gam = ACC ? p.st[k & 1].gamma : 0.0;
+    const double delta = p.delta;
+    const char* __restrict__ pbase = reinterpret_cast<const char*>(p.lpair[k & 1]);
+    double* __restrict__ rec = p.rec;
+    bool bad = false;
+    int run_key = -1;
+    double run0 = 0.0, run1 = 0.0;
+    __syncthreads();
+
+    const int last = end - 1;  // tiles are never empty
+    const int ns = active ? (end - beg + kWave - 1) / kWave : 0;
+    // landmark index of each lane's observation, one step ahead of the fetch;
+    // lane 4r + c fetches chunk c of record 16 i + r in instruction i
+    int li_ahead = 0;
+    auto load_li = [&](int st) { li_ahead = p.obs_lm[min(beg + kWave * st + lane, last)]; };
+    // Lane-derived offsets are recomputed inside each step from a lane index
+    // the optimizer cannot see through: hoisted out of the loop they would
+    // hold VGPRs for its whole length.
+    auto opaque_lane = [&]() {
+        int l = lane;
+        asm volatile("" : "+v"(l));
+        return l;
+    };
+    auto fetch = [&](int st, ObsBuf& D) {
+        const int ln = opaque_lane(), quad = ln >> 2, qc = ln & 3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const unsigned li = (unsigned)__shfl(li_ahead, 16 * i + quad);
+            dma16(pbase + (li * (unsigned)(kLmPair * 8) + 16u * qc), &D.pair[16 * i * kLmPair]);
+        }
+        const unsigned o = (unsigned)min(beg + kWave * st + ln, last);
+        dma16(reinterpret_cast<const char*>(p.uv) + 16u * o, &D.uv[0]);
+        dma4(reinterpret_cast<const char*>(p.obs_slot) + 4u * o, &D.slot[0]);
+    };
+    // records of step st (staged) to their slots (in D, the buffer of step st)
+    auto store_recs = [&](int st, const ObsBuf& D) {
+        const int ln = opaque_lane(), quad = ln >> 2, qc = ln & 3;
+        const int b0 = beg + kWave * st;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * i + quad;
+            if (b0 + r < end) {
+                const double2 v = *reinterpret_cast<const double2*>(&stg[r * 8 + 2 * qc]);
+                *reinterpret_cast<double2*>(rec + (size_t)D.slot[r] * 8 + 2 * qc) = v;
+            }
+        }
+    };
+    // step st reads buffer C; the next step's data goes to N
+    auto step = [&](int st, const ObsBuf& C, ObsBuf& N) {
+        wait_vmem();
+        if (st > 0) store_recs(st - 1, N);
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < ns) {
+            fetch(st + 1, N);
+            if (st + 2 < ns) load_li(st + 2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int ln = opaque_lane();
+        const int o = beg + kWave * st + ln;
+        const bool on = o < end;
+        double hF = 0.0, gp = 0.0;
+        int key = -1;
+        if (on) {
+            const double2 u2 = C.uv[ln];
+            const double* pr = &C.pair[ln * kLmPair];
+            const double2 q0 = *reinterpret_cast<const double2*>(pr);
+            const double2 q1 = *reinterpret_cast<const double2*>(pr + 2);
+            const double lk0 = q0.x, lk1 = q0.y, lk2 = q1.x;
+            const int beta = (int)__double_as_longlong(q1.y);
+            const double ux = u2.x, uy = u2.y;
+            const double r2u = ux * ux + uy * uy, r4u = r2u * r2u;
+            const double r6u = r4u * r2u, r8u = r4u * r4u;
+            double2* sg = reinterpret_cast<double2*>(&stg[ln * 8]);
+            ObsEval<LOSS, double> ek;
+            eval_obs<LOSS, double>(ck, lk0, lk1, lk2, ux, uy, r2u, r4u, delta, ek);
+            bad |= !(ek.r2 > 1e-24);
+            add_moments<double>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
+            // landmark-side record: W = w lambda^2 and V = w lambda e_w per surrogate
+            const double wl = ek.w * ek.lam;
+            sg[0] = make_double2(wl * ek.lam, wl * ek.e[0]);
+            sg[1] = make_double2(wl * ek.e[1], wl * ek.e[2]);
+            if constexpr (ACC) {
+                const double2 q2 = *reinterpret_cast<const double2*>(pr + 4);
+                const double lp2 = pr[6];
+                const double lb0 = lk0 + gam * (lk0 - q2.x);
+                const double lb1 = lk1 + gam * (lk1 - q2.y);
+                const double lb2 = lk2 + gam * (lk2 - lp2);
+                ObsEval<LOSS, double> eb;
+                eval_obs<LOSS, double>(cb, lb0, lb1, lb2, ux, uy, r2u, r4u, delta, eb);
+                bad |= !(eb.r2 > 1e-24);
+                add_moments<double>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
+                const double wb = eb.w * eb.lam;
+                sg[2] = make_double2(wb * eb.lam, wb * eb.e[0]);
+                sg[3] = make_double2(wb * eb.e[1], wb * eb.e[2]);
+            } else {
+                sg[2] = make_double2(0.0, 0.0);
+                sg[3] = make_double2(0.0, 0.0);
+            }
+            // F share: each side of the pair gets half of F_ij = rho / 2
+            hF = 0.25 * ek.rho;
+            key = beta;
+            if (beta != alpha) {
+                // surrogate gap of the previous linearization y = x^(k-1) at x^k:
+                // P - Q = w (|Dc|^2 - |Dl|^2 + e^y . (Dc + Dl)) with
+                // Dc = R^k p^k - R^y p^y + lambda^y (t^k - t^y), Dl = lambda^y (l^k - l^y)
+                const double2 q2 = *reinterpret_cast<const double2*>(pr + 4);
+                const double lp[3] = {q2.x, q2.y, pr[6]};
+                const double lk[3] = {lk0, lk1, lk2};
+                ObsEval<LOSS, double> ep;
+                eval_obs<LOSS, double>(cp, lp[0], lp[1], lp[2], ux, uy, r2u, r4u, delta, ep);
+                // R^k p^k again (cheaper than keeping it live), and the camera
+                // terms as separate products so that no difference of two
+                // loop-invariant values is kept in registers
+                const double pz = ck.d[0] + ck.d[1] * r2u + ck.d[2] * r4u;
+                double q = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double rpk = ck.r[3 * a] * ux + ck.r[3 * a + 1] * uy + ck.r[3 * a + 2] * pz;
+                    const double dc = rpk - ep.Rp[a] + ep.lam * ck.t[a] - ep.lam * cp.t[a];
+                    const double dl = ep.lam * (lk[a] - lp[a]);
+                    q += dc * dc - dl * dl + ep.e[a] * (dc + dl);
+                }
+                gp = 0.5 * ep.w * q;
+            }
+        }
+        acc[2 * kMom] += hF;
+        acc[2 * kMom + 1] += gp;
+        if (S > 1) {
+            // landmark-side shares by landmark partition (see k_obs)
+            const int k0 = uniform_int(key);
+            const bool uni = __all(!on || key == k0);
+            if (uni) {
+                if (k0 != run_key) {
+                    flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
+                    run_key = k0;
+                }
+                run0 += hF;
+                run1 -= gp;
+            } else {
+                flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
+                run_key = -1;
+                bin_add_sorted(hF, -gp, key, lane, bins[0], bins[1]);
+            }
+        }
+    };
+
+    if (ns > 0) {
+        load_li(0);
+        fetch(0, A);
+        if (ns > 1) load_li(1);
+    }
+    for (int st = 0; st < ns; st += 2) {
+        step(st, A, B);
+        if (st + 1 < ns) step(st + 1, B, A);
+    }
+    wait_vmem();
+    if (ns > 0) store_recs(ns - 1, (ns - 1) & 1 ? B : A);
+    if (S > 1) flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
+    if (bad) p.st[0].err = -5;
+
+    // tile totals: LDS transpose in the two pair buffers (rows 0..6 in A,
+    // 7..13 in B), lane v sums value v over the 64 lanes
+    wait_vmem();
+    constexpr int kCh = 2 * kRedHalf;
+#pragma unroll
+    for (int c0 = 0; c0 < kAcc; c0 += kCh) {
+#pragma unroll
+        for (int v = 0; v < kCh; ++v) {
+            if (c0 + v < kAcc) {
+                double* row = v < kRedHalf ? &A.pair[v * (kWave + 1)] : &B.pair[(v - kRedHalf) * (kWave + 1)];
+                row[lane] = acc[c0 + v];
+            }
+        }
+        __syncthreads();
+        if (active && lane < kCh && c0 + lane < kAcc) {
+            const double* row = lane < kRedHalf ? &A.pair[lane * (kWave + 1)]
+                                                : &B.pair[(lane - kRedHalf) * (kWave + 1)];
+            double sum = 0.0;
+            for (int q = 0; q < kWave; ++q) sum += row[q];
+            p.tile_vals[(size_t)t * kTileVals + c0 + lane] = sum;
+        }
+        __syncthreads();
+    }
+    if (active) {
+        if (S == 1) {
+            if (lane == 0) {
+                p.tile_bins[t] = p.tile_vals[(size_t)t * kTileVals + 2 * kMom];
+                p.tile_bins[(size_t)p.T + t] = -p.tile_vals[(size_t)t * kTileVals + 2 * kMom + 1];
+            }
+        } else {
+            for (int b = lane; b < S; b += kWave) {
+                p.tile_bins[(size_t)b * p.T + t] = bins[0][b];
+                p.tile_bins[(size_t)(S + b) * p.T + t] = bins[1][b];
             }
         }
     }
@@ -860,75 +1134,6 @@ __device__ void nearest_rotation(const double* M, double* R) {
 
 // ------------------------------------------------------------ entity pass
 
-// ------------------------------------------------------- restart decision
-
-// One block, after k_entity: per-partition restart metrics and test,
-// the objective trace and the Nesterov scalars.  (A separate launch: a
-// last-block-done decision inside the entity kernels needs a device-scope
-// release fence in every block, which writes back the whole L2 of each XCD
-// and costs more than the launch.)
-__global__ __launch_bounds__(256) void k_decide(Params p, int k) {
-    __shared__ double sFsh[kMaxPart];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int S = p.S;
-    for (int a = wv; a < S; a += 4) {
-        double c0 = 0, c1 = 0, c2 = 0, c3 = 0, l0 = 0, l1 = 0;
-        for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
-            c0 += p.camblk_vals[(size_t)q * 4 + 0];
-            c1 += p.camblk_vals[(size_t)q * 4 + 1];
-            c2 += p.camblk_vals[(size_t)q * 4 + 2];
-            c3 += p.camblk_vals[(size_t)q * 4 + 3];
-        }
-        for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
-            l0 += p.lmblk_vals[(size_t)q * 2 + 0];
-            l1 += p.lmblk_vals[(size_t)q * 2 + 1];
-        }
-        c0 = wave_sum(c0); c1 = wave_sum(c1); c2 = wave_sum(c2); c3 = wave_sum(c3);
-        l0 = wave_sum(l0); l1 = wave_sum(l1);
-        if (lane == 0) {
-            // E^a(x^k | x^k): each pair's F split in halves between its sides
-            const double Fsh = c2 + p.colsum[a];
-            // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
-            const double V = Fsh + c3 + p.colsum[S + a];
-            const double Fk = p.E[a] + V - p.EE[a];                       // eq. Fak
-            const double Fb = (1.0 - p.eta) * p.Fbar[a] + p.eta * Fk;     // eq. lFak
-            const double dmm = c0 + l0, dacc = c1 + l1;
-            int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                 // eq. Eak test
-            if (p.accelerate && (p.flags & 1)) rs = 0;
-            if (p.accelerate && (p.flags & 2)) rs = 1;
-            const double dch = rs ? dmm : dacc;
-            p.Fprev[a] = Fk;
-            p.Fbar[a] = Fb;
-            p.E[a] = Fk + dch;
-            p.EE[a] = Fsh + dch;
-            p.restart[a] = rs;
-            p.metrics[4 * a + 0] = Fk;
-            p.metrics[4 * a + 1] = Fb;
-            p.metrics[4 * a + 2] = Fk + dch;
-            p.metrics[4 * a + 3] = (double)rs;
-            sFsh[a] = Fsh;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double F = 0.0;
-        for (int a = 0; a < S; ++a) F += sFsh[a];
-        DevState* st = p.st;
-        if (!isfinite(F) && st->err == 0) st->err = -4;  // a degenerate point reported first wins
-        st->F = F;
-        const int64_t kk = st->k;
-        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
-        // eq. nesterov_scalar: s^(k+1), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
-        const double s1 = (sqrt(4.0 * st->s * st->s + 1.0) + 1.0) / 2.0;
-        const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
-        st->s = s1;
-        st->gamma = p.accelerate ? (s1 - 1.0) / s2 : 0.0;
-        st->k = kk + 1;
-    }
-}
-
-
 // Camera subproblems of one block of <= 128 cameras in one partition:
 // threads [0,128) solve the plain surrogate, [128,256) the accelerated one.
 template <bool ACC>
@@ -1076,7 +1281,7 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
             cm[1] = L.lk[1] + dl[1];
             cm[2] = L.lk[2] + dl[2];
             if (ACC) {
-                const double gam = p.st->gamma;
+                const double gam = p.st[k & 1].gamma;
                 const double den1 = 2.0 * W1 + xi;
                 double da[3], na = 0.0, va = 0.0;
 #pragma unroll
@@ -1120,11 +1325,98 @@ __device__ void extrapolate_cam(const double* cn, const double* co, double gam, 
     out[15] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_select(Params p, int k) {
+// Per-partition restart metrics and test (eq. Fak, lFak, Eak) from the
+// block sums of k_entity, for all S partitions; every block of the selection
+// computes them (in the same order, so identically) and block 0 stores them.
+// The bookkeeping is double-buffered by iteration parity: iteration k reads
+// slot k & 1 and writes slot (k + 1) & 1, so no block can see a half-updated
+// state.  (One decision kernel ahead of the selection would cost a launch; a
+// last-block-done decision inside k_entity would need a device-scope release
+// fence in every block, which writes back each XCD's whole L2.)
+__device__ void decide(const Params& p, int k, bool writer, int* s_rs, double* s_Fsh) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int S = p.S;
+    const int cur = (k & 1) * S, nxt = ((k + 1) & 1) * S;
+    for (int a = wv; a < S; a += 4) {
+        double c0 = 0, c1 = 0, c2 = 0, c3 = 0, l0 = 0, l1 = 0;
+        for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
+            c0 += p.camblk_vals[(size_t)q * 4 + 0];
+            c1 += p.camblk_vals[(size_t)q * 4 + 1];
+            c2 += p.camblk_vals[(size_t)q * 4 + 2];
+            c3 += p.camblk_vals[(size_t)q * 4 + 3];
+        }
+        for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
+            l0 += p.lmblk_vals[(size_t)q * 2 + 0];
+            l1 += p.lmblk_vals[(size_t)q * 2 + 1];
+        }
+        c0 = wave_sum(c0); c1 = wave_sum(c1); c2 = wave_sum(c2); c3 = wave_sum(c3);
+        l0 = wave_sum(l0); l1 = wave_sum(l1);
+        if (lane == 0) {
+            // E^a(x^k | x^k): each pair's F split in halves between its sides
+            const double Fsh = c2 + p.colsum[a];
+            // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
+            const double V = Fsh + c3 + p.colsum[S + a];
+            const double Fk = p.E[cur + a] + V - p.EE[cur + a];              // eq. Fak
+            const double Fb = (1.0 - p.eta) * p.Fbar[cur + a] + p.eta * Fk;  // eq. lFak
+            const double dmm = c0 + l0, dacc = c1 + l1;
+            int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                    // eq. Eak test
+            if (p.accelerate && (p.flags & 1)) rs = 0;
+            if (p.accelerate && (p.flags & 2)) rs = 1;
+            const double dch = rs ? dmm : dacc;
+            s_rs[a] = rs;
+            s_Fsh[a] = Fsh;
+            if (writer) {
+                p.Fprev[nxt + a] = Fk;
+                p.Fbar[nxt + a] = Fb;
+                p.E[nxt + a] = Fk + dch;
+                p.EE[nxt + a] = Fsh + dch;
+                p.metrics[4 * a + 0] = Fk;
+                p.metrics[4 * a + 1] = Fb;
+                p.metrics[4 * a + 2] = Fk + dch;
+                p.metrics[4 * a + 3] = (double)rs;
+            }
+        }
+    }
+}
+
+// eq. nesterov_scalar: s^(k+1) from s^(k), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
+__device__ __forceinline__ double next_gamma(const Params& p, double s, double* s1_out) {
+    const double s1 = (sqrt(4.0 * s * s + 1.0) + 1.0) / 2.0;
+    const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
+    *s1_out = s1;
+    return p.accelerate ? (s1 - 1.0) / s2 : 0.0;
+}
+
+// After k_entity: the restart decision (every block, see decide), then each
+// partition's candidate is taken (eq. update_amm or update_mm), the iterates
+// roll, cameras are extrapolated for the next iteration (eq. nesterov_x) and
+// the landmark pair records for it are written.
+__global__ __launch_bounds__(256) void k_decide_select(Params p, int k) {
+    __shared__ int s_rs[kMaxPart];
+    __shared__ double s_Fsh[kMaxPart];
+    const bool writer = blockIdx.x == 0;
+    decide(p, k, writer, s_rs, s_Fsh);
+    __syncthreads();
+    const DevState& sc = p.st[k & 1];
+    double s1;
+    const double gam = next_gamma(p, sc.s, &s1);
+    if (writer && threadIdx.x == 0) {
+        double F = 0.0;
+        for (int a = 0; a < p.S; ++a) F += s_Fsh[a];
+        if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
+        const int64_t kk = sc.k;
+        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
+        DevState& sn = p.st[(k + 1) & 1];
+        sn.F = F;
+        sn.s = s1;
+        sn.gamma = gam;
+        sn.k = kk + 1;
+    }
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < p.M) {
         const int ci = (int)i;
-        const int rs = p.accelerate ? p.restart[p.cam_part[ci]] : 1;
+        const int rs = p.accelerate ? s_rs[p.cam_part[ci]] : 1;
         const double* src = p.cam_cand[rs ? 0 : 1] + (size_t)ci * kCamRec;
         double* dst = p.cams[(k + 1) % 3] + (size_t)ci * kCamRec;
         const double* cur = p.cams[k % 3] + (size_t)ci * kCamRec;
@@ -1136,7 +1428,7 @@ __global__ __launch_bounds__(256) void k_select(Params p, int k) {
         for (int a = 0; a < 16; ++a) dst[a] = cn[a];
         if (p.accelerate) {
             double cb[16];
-            extrapolate_cam(cn, cur, p.st->gamma, cb);
+            extrapolate_cam(cn, cur, gam, cb);
 #pragma unroll
             for (int a = 0; a < 16; ++a) p.cam_bar[(size_t)ci * kCamRec + a] = cb[a];
         }
@@ -1145,10 +1437,13 @@ __global__ __launch_bounds__(256) void k_select(Params p, int k) {
     const int64_t j = i - p.M;
     if (j < p.N) {
         const int li = (int)j;
+        // both candidates are loaded with the pair, so the choice costs no
+        // second memory round trip
+        const double4 cm = *reinterpret_cast<const double4*>(p.lcand[0] + (size_t)li * 4);
+        const double4 ca = *reinterpret_cast<const double4*>(p.lcand[1] + (size_t)li * 4);
         const LmRead<double> L = read_pair(p.lpair[k & 1], li);
-        const int rs = p.accelerate ? p.restart[L.beta] : 1;
-        const double* c = p.lcand[rs ? 0 : 1] + (size_t)li * 4;
-        double ln[3] = {c[0], c[1], c[2]};
+        const int rs = p.accelerate ? s_rs[L.beta] : 1;
+        const double ln[3] = {rs ? cm.x : ca.x, rs ? cm.y : ca.y, rs ? cm.z : ca.z};
         double2* q = reinterpret_cast<double2*>(p.lpair[(k + 1) & 1] + (size_t)li * kLmPair);
         q[0] = make_double2(ln[0], ln[1]);
         q[1] = make_double2(ln[2], __longlong_as_double((long long)L.beta));
@@ -1167,7 +1462,7 @@ __global__ __launch_bounds__(256) void k_extrapolate_cams(Params p, int k) {
     if (ci >= p.M) return;
     double cb[16];
     extrapolate_cam(p.cams[k % 3] + (size_t)ci * kCamRec, p.cams[(k + 2) % 3] + (size_t)ci * kCamRec,
-                    p.st->gamma, cb);
+                    p.st[k & 1].gamma, cb);
 #pragma unroll
     for (int a = 0; a < 16; ++a) p.cam_bar[(size_t)ci * kCamRec + a] = cb[a];
 }
@@ -1214,7 +1509,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_objective(Params p, const 
         acc += hF;
         if (bins_out) bin_add_sorted(hF, 0.0, key, lane, bins[wv][0], bins[wv][1]);
     }
-    if (bad) p.st->err = -5;
+    if (bad) p.st[0].err = -5;
     acc = wave_sum(acc);
     if (lane == 0) tile_F[t] = acc;
     if (bins_out)
@@ -1257,7 +1552,7 @@ __global__ __launch_bounds__(256) void k_objective_reduce(Params p, const double
         double F = 0.0;
         for (int a = 0; a < S; ++a) F += sp[a];
         *F_out = F;
-        if (!isfinite(F) && p.st->err == 0) p.st->err = -4;
+        if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;
     }
 }
 
@@ -1439,8 +1734,8 @@ hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s) {
             if (p.accelerate) hipLaunchKernelGGL((k_obs<float, LS, true>), grid, block, 0, s, p, k);
             else hipLaunchKernelGGL((k_obs<float, LS, false>), grid, block, 0, s, p, k);
         } else {
-            if (p.accelerate) hipLaunchKernelGGL((k_obs<double, LS, true>), grid, block, 0, s, p, k);
-            else hipLaunchKernelGGL((k_obs<double, LS, false>), grid, block, 0, s, p, k);
+            if (p.accelerate) hipLaunchKernelGGL((k_obs64<LS, true>), dim3(p.T), dim3(kWave), 0, s, p, k);
+            else hipLaunchKernelGGL((k_obs64<LS, false>), dim3(p.T), dim3(kWave), 0, s, p, k);
         }
     });
     return hipGetLastError();
@@ -1458,14 +1753,9 @@ hipError_t launch_entity(const Params& p, int k, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_decide(const Params& p, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, p, k);
-    return hipGetLastError();
-}
-
-hipError_t launch_select(const Params& p, int k, hipStream_t s) {
+hipError_t launch_decide_select(const Params& p, int k, hipStream_t s) {
     const int64_t n = p.M + p.N;
-    hipLaunchKernelGGL(k_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, k);
+    hipLaunchKernelGGL(k_decide_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, k);
     return hipGetLastError();
 }
 

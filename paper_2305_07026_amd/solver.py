@@ -106,7 +106,7 @@ class DabaSolver:
 
     def iterate_timed(self, n: int):
         """n iterations; returns summed GPU ms of (observation pass, entity
-        solves with the restart test, selection)."""
+        solves, restart test with the selection)."""
         ms = np.zeros(3)
         self._chk(B.lib.daba_iterate_timed(self._h, n, _ptr(ms, C.c_double)), "daba_iterate_timed")
         return ms
