@@ -269,6 +269,7 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.cam_bar = c.take<double>(M * kCamRec);
     p.cam_cand[0] = c.take<double>(M * kCamRec);
     p.cam_cand[1] = c.take<double>(M * kCamRec);
+    for (int q = 0; q < 2; ++q) p.cam_bar_cand[q] = c.take<double>(M * kCamRec);
     p.lpair[0] = c.take<double>(N * kLmPair);
     p.lpair[1] = c.take<double>(N * kLmPair);
     p.lpair32[0] = fp32 ? c.take<float>(N * kLmPair) : nullptr;
@@ -504,6 +505,8 @@ size_t daba_workspace_bytes(const daba_problem* prob, const daba_options* opt) {
     }
 }
 
+static bool ensure_period_graph(daba_handle* h);
+
 int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_workspace, size_t workspace_bytes,
                 void* hip_stream, daba_handle** out) {
     if (!out) {
@@ -614,6 +617,8 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         write_point(h, prob->cameras, prob->landmarks, prob->cameras, prob->landmarks);
         hipcheck(launch_extrapolate_cams(p, 0, s), "extrapolate");
         init_metrics(h);
+        // capture the replayed period now, so that no later call pays for it
+        ensure_period_graph(h);
         *out = h;
         return DABA_OK;
     } catch (const Fail& f) {

@@ -87,6 +87,7 @@ struct Params {
     double* cams[3];
     double* cam_bar;
     double* cam_cand[2];      // 0: plain MM, 1: accelerated
+    double* cam_bar_cand[2];  // x-bar^(k+1) if candidate 0 / 1 is chosen
     double* lpair[2];
     float* lpair32[2];
     double* lcand[2];

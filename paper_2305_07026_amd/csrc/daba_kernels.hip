@@ -1134,6 +1134,28 @@ __device__ void nearest_rotation(const double* M, double* R) {
 
 // ------------------------------------------------------------ entity pass
 
+// x-bar for the next iteration from a camera's next and current values (eq.
+// nesterov_x with the rotation projected by eq. proj_rot3d)
+__device__ void extrapolate_cam(const double* cn, const double* co, double gam, double* out) {
+    double Mx[9], Rb[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Mx[a] = cn[a] + gam * (cn[a] - co[a]);
+    if (!polar_rotation(Mx, Rb)) nearest_rotation(Mx, Rb);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[a] = Rb[a];
+#pragma unroll
+    for (int a = 9; a < 15; ++a) out[a] = cn[a] + gam * (cn[a] - co[a]);
+    out[15] = 0.0;
+}
+
+// eq. nesterov_scalar: s^(k+1) from s^(k), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
+__device__ __forceinline__ double next_gamma(const Params& p, double s, double* s1_out) {
+    const double s1 = (sqrt(4.0 * s * s + 1.0) + 1.0) / 2.0;
+    const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
+    *s1_out = s1;
+    return p.accelerate ? (s1 - 1.0) / s2 : 0.0;
+}
+
 // Camera subproblems of one block of <= 128 cameras in one partition:
 // threads [0,128) solve the plain surrogate, [128,256) the accelerated one.
 template <bool ACC>
@@ -1161,6 +1183,25 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, doubl
         const CamD y = surr == 0 ? ck : load_camd(p.cam_bar + (size_t)ci * kCamRec);
         const CamD c = lm_camera(mom, y, xi, p.inner_steps);
         store_camd(p.cam_cand[surr] + (size_t)ci * kCamRec, c);
+        if constexpr (ACC) {
+            // the extrapolation the next iteration uses if this candidate is
+            // chosen; gamma^(k+1) depends only on s^(k), so it is known now
+            double s1;
+            const double gnext = next_gamma(p, p.st[k & 1].s, &s1);
+            double cn[16], cbar[16];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) cn[a] = c.R[a];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cn[9 + a] = c.t[a];
+                cn[12 + a] = c.d[a];
+            }
+            cn[15] = 0.0;
+            extrapolate_cam(cn, p.cams[k % 3] + (size_t)ci * kCamRec, gnext, cbar);
+            double* dst = p.cam_bar_cand[surr] + (size_t)ci * kCamRec;
+#pragma unroll
+            for (int a = 0; a < 16; ++a) dst[a] = cbar[a];
+        }
         if (surr == 1) {
             // the plain surrogate (about x^k) at the accelerated candidate
 #pragma unroll
@@ -1194,13 +1235,13 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, doubl
     }
 }
 
-// Sums a landmark's records (slots base + q n + lane, q < D), four in flight
+// Sums a landmark's records (slots base + q n + lane, q < D), eight in flight
 // per lane; FP32 records are accumulated in FP64.
 template <typename RT, bool ACC>
 __device__ __forceinline__ void sum_records(const RT* __restrict__ rec, int64_t base, int n, int lane, int D,
                                             double& W0, double* V0, double& W1, double* V1) {
     using V4 = typename std::conditional<std::is_same<RT, double>::value, double4, float4>::type;
-    constexpr int U = 4;
+    constexpr int U = 8;  // the camera role already sets this kernel's VGPR budget
     for (int q0 = 0; q0 < D; q0 += U) {
         V4 ra[U], rb[U];
 #pragma unroll
@@ -1313,18 +1354,6 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
 
 // ------------------------------------------------------- select and roll
 
-__device__ void extrapolate_cam(const double* cn, const double* co, double gam, double* out) {
-    double Mx[9], Rb[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) Mx[a] = cn[a] + gam * (cn[a] - co[a]);
-    if (!polar_rotation(Mx, Rb)) nearest_rotation(Mx, Rb);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) out[a] = Rb[a];
-#pragma unroll
-    for (int a = 9; a < 15; ++a) out[a] = cn[a] + gam * (cn[a] - co[a]);
-    out[15] = 0.0;
-}
-
 // Per-partition restart metrics and test (eq. Fak, lFak, Eak) from the
 // block sums of k_entity, for all S partitions; every block of the selection
 // computes them (in the same order, so identically) and block 0 stores them.
@@ -1333,77 +1362,131 @@ __device__ void extrapolate_cam(const double* cn, const double* co, double gam, 
 // state.  (One decision kernel ahead of the selection would cost a launch; a
 // last-block-done decision inside k_entity would need a device-scope release
 // fence in every block, which writes back each XCD's whole L2.)
-__device__ void decide(const Params& p, int k, bool writer, int* s_rs, double* s_Fsh) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int S = p.S;
-    const int cur = (k & 1) * S, nxt = ((k + 1) & 1) * S;
-    for (int a = wv; a < S; a += 4) {
-        double c0 = 0, c1 = 0, c2 = 0, c3 = 0, l0 = 0, l1 = 0;
-        for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
-            c0 += p.camblk_vals[(size_t)q * 4 + 0];
-            c1 += p.camblk_vals[(size_t)q * 4 + 1];
-            c2 += p.camblk_vals[(size_t)q * 4 + 2];
-            c3 += p.camblk_vals[(size_t)q * 4 + 3];
-        }
-        for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
-            l0 += p.lmblk_vals[(size_t)q * 2 + 0];
-            l1 += p.lmblk_vals[(size_t)q * 2 + 1];
-        }
-        c0 = wave_sum(c0); c1 = wave_sum(c1); c2 = wave_sum(c2); c3 = wave_sum(c3);
-        l0 = wave_sum(l0); l1 = wave_sum(l1);
-        if (lane == 0) {
-            // E^a(x^k | x^k): each pair's F split in halves between its sides
-            const double Fsh = c2 + p.colsum[a];
-            // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
-            const double V = Fsh + c3 + p.colsum[S + a];
-            const double Fk = p.E[cur + a] + V - p.EE[cur + a];              // eq. Fak
-            const double Fb = (1.0 - p.eta) * p.Fbar[cur + a] + p.eta * Fk;  // eq. lFak
-            const double dmm = c0 + l0, dacc = c1 + l1;
-            int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                    // eq. Eak test
-            if (p.accelerate && (p.flags & 1)) rs = 0;
-            if (p.accelerate && (p.flags & 2)) rs = 1;
-            const double dch = rs ? dmm : dacc;
-            s_rs[a] = rs;
-            s_Fsh[a] = Fsh;
-            if (writer) {
-                p.Fprev[nxt + a] = Fk;
-                p.Fbar[nxt + a] = Fb;
-                p.E[nxt + a] = Fk + dch;
-                p.EE[nxt + a] = Fsh + dch;
-                p.metrics[4 * a + 0] = Fk;
-                p.metrics[4 * a + 1] = Fb;
-                p.metrics[4 * a + 2] = Fk + dch;
-                p.metrics[4 * a + 3] = (double)rs;
-            }
-        }
+struct DecideLds {
+    int camblk[kMaxPart + 1], lmblk[kMaxPart + 1];  // block ranges of each partition
+    double E[kMaxPart], EE[kMaxPart], Fbar[kMaxPart], col0[kMaxPart], col1[kMaxPart];
+    int rs[kMaxPart];
+    double Fsh[kMaxPart];
+};
+
+// Sums of the camera-block and landmark-block values of partition a (lane
+// partials; the caller reduces over the wave).
+__device__ __forceinline__ void part_sums(const Params& p, const DecideLds& d, int a, int lane, double* c, double* l) {
+    for (int q = d.camblk[a] + lane; q < d.camblk[a + 1]; q += kWave) {
+        const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)q * 4);
+        c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
+    }
+    for (int q = d.lmblk[a] + lane; q < d.lmblk[a + 1]; q += kWave) {
+        const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)q * 2);
+        l[0] += v.x; l[1] += v.y;
     }
 }
 
-// eq. nesterov_scalar: s^(k+1) from s^(k), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
-__device__ __forceinline__ double next_gamma(const Params& p, double s, double* s1_out) {
-    const double s1 = (sqrt(4.0 * s * s + 1.0) + 1.0) / 2.0;
-    const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
-    *s1_out = s1;
-    return p.accelerate ? (s1 - 1.0) / s2 : 0.0;
+__device__ __forceinline__ void decide_one(const Params& p, int k, bool writer, DecideLds& d, int a,
+                                           const double* c, const double* l) {
+    const int S = p.S;
+    const int nxt = ((k + 1) & 1) * S;
+    // E^a(x^k | x^k): each pair's F split in halves between its sides
+    const double Fsh = c[2] + d.col0[a];
+    // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
+    const double V = Fsh + c[3] + d.col1[a];
+    const double Fk = d.E[a] + V - d.EE[a];                       // eq. Fak
+    const double Fb = (1.0 - p.eta) * d.Fbar[a] + p.eta * Fk;     // eq. lFak
+    const double dmm = c[0] + l[0], dacc = c[1] + l[1];
+    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                 // eq. Eak test
+    if (p.accelerate && (p.flags & 1)) rs = 0;
+    if (p.accelerate && (p.flags & 2)) rs = 1;
+    const double dch = rs ? dmm : dacc;
+    d.rs[a] = rs;
+    d.Fsh[a] = Fsh;
+    if (writer) {
+        p.Fprev[nxt + a] = Fk;
+        p.Fbar[nxt + a] = Fb;
+        p.E[nxt + a] = Fk + dch;
+        p.EE[nxt + a] = Fsh + dch;
+        p.metrics[4 * a + 0] = Fk;
+        p.metrics[4 * a + 1] = Fb;
+        p.metrics[4 * a + 2] = Fk + dch;
+        p.metrics[4 * a + 3] = (double)rs;
+    }
 }
 
-// After k_entity: the restart decision (every block, see decide), then each
-// partition's candidate is taken (eq. update_amm or update_mm), the iterates
-// roll, cameras are extrapolated for the next iteration (eq. nesterov_x) and
-// the landmark pair records for it are written.
-__global__ __launch_bounds__(256) void k_decide_select(Params p, int k) {
-    __shared__ int s_rs[kMaxPart];
-    __shared__ double s_Fsh[kMaxPart];
-    const bool writer = blockIdx.x == 0;
-    decide(p, k, writer, s_rs, s_Fsh);
+// Every block: bookkeeping into LDS in one round, then each wave sums two
+// partitions at a time (their loads in flight together).
+__device__ void decide(const Params& p, int k, bool writer, DecideLds& d) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int S = p.S;
+    const int cur = (k & 1) * S;
+    const int tid = threadIdx.x;
+    if (tid <= S) {
+        d.camblk[tid] = p.part_camblk[tid];
+        d.lmblk[tid] = p.part_lmblk[tid];
+    }
+    if (tid < S) {
+        d.E[tid] = p.E[cur + tid];
+        d.EE[tid] = p.EE[cur + tid];
+        d.Fbar[tid] = p.Fbar[cur + tid];
+        d.col0[tid] = p.colsum[tid];
+        d.col1[tid] = p.colsum[S + tid];
+    }
     __syncthreads();
+    for (int a0 = wv; a0 < S; a0 += 8) {
+        const int a1 = a0 + 4;
+        double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
+        part_sums(p, d, a0, lane, c0, l0);
+        if (a1 < S) part_sums(p, d, a1, lane, c1, l1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c0[q] = wave_sum(c0[q]);
+            c1[q] = wave_sum(c1[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            l0[q] = wave_sum(l0[q]);
+            l1[q] = wave_sum(l1[q]);
+        }
+        if (lane == 0) {
+            decide_one(p, k, writer, d, a0, c0, l0);
+            if (a1 < S) decide_one(p, k, writer, d, a1, c1, l1);
+        }
+    }
+    __syncthreads();
+}
+
+// After k_entity: each thread first loads what it may select (both
+// candidates), then the restart decision is taken (every block, see decide),
+// then each partition's candidate is kept (eq. update_amm or update_mm), the
+// iterates roll and the next iteration's pair records and extrapolated
+// cameras are written.
+__global__ __launch_bounds__(256) void k_decide_select(Params p, int k) {
+    __shared__ DecideLds d;
+    const bool writer = blockIdx.x == 0;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool is_cam = i < p.M;
+    const bool is_lm = !is_cam && i - p.M < p.N;
+    const int ci = (int)i;
+    const int li = (int)(i - p.M);
+    // landmark: the pair record and both candidates
+    double2 q0 = {}, q1 = {}, cm0 = {}, cm1 = {}, ca0 = {}, ca1 = {};
+    if (is_lm) {
+        const double2* pr = reinterpret_cast<const double2*>(p.lpair[k & 1] + (size_t)li * kLmPair);
+        q0 = pr[0];
+        q1 = pr[1];
+        const double2* m = reinterpret_cast<const double2*>(p.lcand[0] + (size_t)li * 4);
+        const double2* c = reinterpret_cast<const double2*>(p.lcand[1] + (size_t)li * 4);
+        cm0 = m[0];
+        cm1 = m[1];
+        ca0 = c[0];
+        ca1 = c[1];
+    }
+    decide(p, k, writer, d);
     const DevState& sc = p.st[k & 1];
-    double s1;
-    const double gam = next_gamma(p, sc.s, &s1);
     if (writer && threadIdx.x == 0) {
+        double s1;
+        const double gam = next_gamma(p, sc.s, &s1);
         double F = 0.0;
-        for (int a = 0; a < p.S; ++a) F += s_Fsh[a];
+        for (int a = 0; a < p.S; ++a) F += d.Fsh[a];
         if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
         const int64_t kk = sc.k;
         if (kk >= 0) p.trace[kk % p.trace_cap] = F;
@@ -1413,46 +1496,34 @@ __global__ __launch_bounds__(256) void k_decide_select(Params p, int k) {
         sn.gamma = gam;
         sn.k = kk + 1;
     }
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < p.M) {
-        const int ci = (int)i;
-        const int rs = p.accelerate ? s_rs[p.cam_part[ci]] : 1;
-        const double* src = p.cam_cand[rs ? 0 : 1] + (size_t)ci * kCamRec;
-        double* dst = p.cams[(k + 1) % 3] + (size_t)ci * kCamRec;
-        const double* cur = p.cams[k % 3] + (size_t)ci * kCamRec;
-        double cn[16];
+    if (is_cam) {
+        const int rs = p.accelerate ? d.rs[p.cam_part[ci]] : 1;
+        // the chosen candidate and its extrapolation (computed in k_entity)
+        const double2* src = reinterpret_cast<const double2*>(p.cam_cand[rs ? 0 : 1] + (size_t)ci * kCamRec);
+        double2* dst = reinterpret_cast<double2*>(p.cams[(k + 1) % 3] + (size_t)ci * kCamRec);
 #pragma unroll
-        for (int a = 0; a < 15; ++a) cn[a] = src[a];
-        cn[15] = 0.0;
-#pragma unroll
-        for (int a = 0; a < 16; ++a) dst[a] = cn[a];
+        for (int a = 0; a < 8; ++a) dst[a] = src[a];
         if (p.accelerate) {
-            double cb[16];
-            extrapolate_cam(cn, cur, gam, cb);
+            const double2* sb = reinterpret_cast<const double2*>(p.cam_bar_cand[rs ? 0 : 1] + (size_t)ci * kCamRec);
+            double2* db = reinterpret_cast<double2*>(p.cam_bar + (size_t)ci * kCamRec);
 #pragma unroll
-            for (int a = 0; a < 16; ++a) p.cam_bar[(size_t)ci * kCamRec + a] = cb[a];
+            for (int a = 0; a < 8; ++a) db[a] = sb[a];
         }
         return;
     }
-    const int64_t j = i - p.M;
-    if (j < p.N) {
-        const int li = (int)j;
-        // both candidates are loaded with the pair, so the choice costs no
-        // second memory round trip
-        const double4 cm = *reinterpret_cast<const double4*>(p.lcand[0] + (size_t)li * 4);
-        const double4 ca = *reinterpret_cast<const double4*>(p.lcand[1] + (size_t)li * 4);
-        const LmRead<double> L = read_pair(p.lpair[k & 1], li);
-        const int rs = p.accelerate ? s_rs[L.beta] : 1;
-        const double ln[3] = {rs ? cm.x : ca.x, rs ? cm.y : ca.y, rs ? cm.z : ca.z};
+    if (is_lm) {
+        const int beta = (int)__double_as_longlong(q1.y);
+        const int rs = p.accelerate ? d.rs[beta] : 1;
+        const double2 n0 = rs ? cm0 : ca0, n1 = rs ? cm1 : ca1;  // next l: (x, y), (z, -)
         double2* q = reinterpret_cast<double2*>(p.lpair[(k + 1) & 1] + (size_t)li * kLmPair);
-        q[0] = make_double2(ln[0], ln[1]);
-        q[1] = make_double2(ln[2], __longlong_as_double((long long)L.beta));
-        q[2] = make_double2(L.lk[0], L.lk[1]);
-        q[3] = make_double2(L.lk[2], 0.0);
+        q[0] = n0;
+        q[1] = make_double2(n1.x, q1.y);
+        q[2] = q0;
+        q[3] = make_double2(q1.x, 0.0);
         if (p.fp32) {
             float4* f = reinterpret_cast<float4*>(p.lpair32[(k + 1) & 1] + (size_t)li * kLmPair);
-            f[0] = make_float4((float)ln[0], (float)ln[1], (float)ln[2], __int_as_float(L.beta));
-            f[1] = make_float4((float)L.lk[0], (float)L.lk[1], (float)L.lk[2], 0.0f);
+            f[0] = make_float4((float)n0.x, (float)n0.y, (float)n1.x, __int_as_float(beta));
+            f[1] = make_float4((float)q0.x, (float)q0.y, (float)q1.x, 0.0f);
         }
     }
 }
