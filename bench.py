@@ -179,7 +179,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes_per_launch": nbytes,
                      "avg_launch_ms": kern[0]},
-        "kernel_ms_per_step": {"k_obs": kern[0], "k_entity": kern[1], "k_decide_select": kern[2]},
+        "kernel_ms_per_step": {"k_obs": kern[0], "k_entity": kern[1]},
+        "k_finalize_ms_per_call": kern[2] * args.steps,
         "wall_s_timed_region": wall,
         "setup_s": setup_s,
         "F_after": F_final,

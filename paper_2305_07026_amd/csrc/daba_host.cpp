@@ -38,7 +38,7 @@ struct Layout {
     std::vector<int> cam_off;                   // [M+1] internal obs offsets
     std::vector<int> tile_cam, tile_begin, tile_end, cam_tile_off;
     std::vector<int> camblock_c0, camblock_c1, part_camblk;
-    std::vector<int> lmblock_g0, lmblock_g1, part_lmblk;
+    std::vector<int> lmblock_g0, lmblock_g1, part_lmblk, lmblock_part;
     int T = 0, G = 0;
 };
 
@@ -68,8 +68,8 @@ void hipcheck(hipError_t e, const char* what) {
 void validate_sizes(const daba_problem* p) {
     if (!p) fail(DABA_E_INVAL, "problem is NULL");
     if (p->n_cameras < 1 || p->n_landmarks < 1 || p->n_obs < 0) fail(DABA_E_INVAL, "need M >= 1, N >= 1, K >= 0");
-    if (p->n_cameras > (1 << 30) || p->n_landmarks > (1 << 30) || p->n_obs > 2000000000LL)
-        fail(DABA_E_INVAL, "problem too large for 32-bit indices");
+    if (p->n_cameras > (1 << 30) || p->n_landmarks > kLmMask || p->n_obs > 2000000000LL)
+        fail(DABA_E_INVAL, "problem too large (at most 2^30 cameras, 2^%d - 1 landmarks, 2e9 observations)", kLmBits);
     if (p->n_partitions < 1 || p->n_partitions > DABA_MAX_PARTITIONS)
         fail(DABA_E_INVAL, "n_partitions must be in [1, %d]", DABA_MAX_PARTITIONS);
     if (p->n_obs > 0 && (!p->obs_camera || !p->obs_landmark)) fail(DABA_E_INVAL, "observation lists are NULL");
@@ -181,7 +181,7 @@ void build_layout(const daba_problem* p, Layout& L) {
         for (int64_t q = 0; q < K; ++q) {
             int li = L.lm_int[p->obs_landmark[L.obs_order[q]]];
             int g = gid[li];
-            L.obs_lm[q] = li;
+            L.obs_lm[q] = li | (L.lpart[L.lm_ext[li]] << kLmBits);
             L.obs_slot[q] = (int)(L.group_base[g] + (int64_t)used[li]++ * L.group_n[g] + lane[li]);
         }
     }
@@ -221,6 +221,7 @@ void build_layout(const daba_problem* p, Layout& L) {
             for (int q = g0; q < g; q += kLmWaves) {
                 L.lmblock_g0.push_back(q);
                 L.lmblock_g1.push_back(std::min(q + kLmWaves, g));
+                L.lmblock_part.push_back(a);
             }
         }
         L.part_lmblk[S] = (int)L.lmblock_g0.size();
@@ -263,19 +264,27 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.camblock_c1 = c.take<int>(L.camblock_c0.size());
     p.part_camblk = c.take<int>(S + 1);
     p.part_lmblk = c.take<int>(S + 1);
+    p.lmblock_part = c.take<int>(L.lmblock_g0.size());
     p.cam_ext = c.take<int>(M);
     p.lm_ext = c.take<int>(N);
+    p.lm_part = c.take<int>(N);
     for (int g = 0; g < 3; ++g) p.cams[g] = c.take<double>(M * kCamRec);
-    p.cam_bar = c.take<double>(M * kCamRec);
-    p.cam_cand[0] = c.take<double>(M * kCamRec);
-    p.cam_cand[1] = c.take<double>(M * kCamRec);
-    for (int q = 0; q < 2; ++q) p.cam_bar_cand[q] = c.take<double>(M * kCamRec);
-    p.lpair[0] = c.take<double>(N * kLmPair);
-    p.lpair[1] = c.take<double>(N * kLmPair);
-    p.lpair32[0] = fp32 ? c.take<float>(N * kLmPair) : nullptr;
-    p.lpair32[1] = fp32 ? c.take<float>(N * kLmPair) : nullptr;
-    p.lcand[0] = c.take<double>(N * 4);
-    p.lcand[1] = c.take<double>(N * 4);
+    for (int par = 0; par < 2; ++par)
+        for (int q = 0; q < 2; ++q) {
+            p.ccand[par][q] = c.take<double>(M * kCamRec);
+            p.cbar[par][q] = c.take<double>(M * kCamRec);
+        }
+    // the two candidates of a parity are one allocation (the observation
+    // pass addresses candidate 1 as candidate 0 plus N records)
+    for (int par = 0; par < 2; ++par) {
+        double* b = c.take<double>(2 * N * kLmPair);
+        p.lcp[par][0] = b;
+        p.lcp[par][1] = b ? b + N * kLmPair : nullptr;
+        float* bf = fp32 ? c.take<float>(2 * N * kLmPair) : nullptr;
+        p.lcp32[par][0] = bf;
+        p.lcp32[par][1] = bf ? bf + N * kLmPair : nullptr;
+    }
+    p.restart = c.take<int>(S);
     p.rec = c.take<double>(K * 8);
     p.rec32 = fp32 ? c.take<float>(K * 8) : nullptr;
     p.tile_vals = c.take<double>(std::max<size_t>(T * kTileVals, 1));
@@ -394,67 +403,117 @@ void sync_and_check(daba_handle* h) {
     if (st.err != 0) fail(DABA_E_HIP, "device error %d", st.err);
 }
 
-// x^k, x^(k-1) and the landmark partition ids into the rotating buffers for
-// iteration counter k; extrapolated cameras follow from gamma in the state.
+// Buffers the current point lives in between calls (iteration counter k):
+// cameras in generations k % 3 (x^k) and (k + 2) % 3 (x^(k-1)), landmark pair
+// records (l^k, partition, l^(k-1)) in candidate slot 0 of parity (k + 1) & 1.
+const double* cur_pair(const daba_handle* h) { return h->p.lcp[(h->k + 1) & 1][0]; }
+
+// x^k and x^(k-1) (caller order and units, all four arrays) into every buffer
+// iteration k reads: camera generations k % 3 and (k + 2) % 3, both camera
+// candidate slots of parity (k + 1) & 1, and both landmark candidate slots as
+// pair records (l^k, partition, l^(k-1)); both x-bar slots follow from
+// gamma^(k) in the state.  Marks the restart test as taken.
 void write_point(daba_handle* h, const double* cams, const double* lms, const double* cams_prev,
                  const double* lms_prev) {
     const Layout& L = h->L;
     Params& p = h->p;
     const double s = p.scale;
-    const int64_t k = h->k;
-    if (cams || cams_prev) {
-        std::vector<double> buf(L.M * kCamRec);
-        for (int which = 0; which < 2; ++which) {
-            const double* src = which == 0 ? cams : cams_prev;
-            if (!src) continue;
-            for (int64_t ci = 0; ci < L.M; ++ci) {
-                const double* c = src + (size_t)L.cam_ext[ci] * 15;
-                for (int a = 0; a < 15; ++a)
-                    if (!std::isfinite(c[a])) fail(DABA_E_INVAL, "camera %d has a non-finite entry", L.cam_ext[ci]);
-                if (!rotation_ok(c)) fail(DABA_E_INVAL, "camera %d: R is not a rotation", L.cam_ext[ci]);
-                cam_to_internal(c, s, &buf[(size_t)ci * kCamRec]);
-            }
-            double* dst = which == 0 ? p.cams[k % 3] : p.cams[(k + 2) % 3];
-            upload(dst, buf.data(), buf.size() * sizeof(double), h->stream);
-            hipcheck(hipStreamSynchronize(h->stream), "sync");
+    const int k = (int)(h->k % 6);
+    const int par = (k + 1) & 1;
+    hipStream_t st = h->stream;
+    std::vector<double> buf(L.M * kCamRec);
+    for (int which = 0; which < 2; ++which) {
+        const double* src = which == 0 ? cams : cams_prev;
+        for (int64_t ci = 0; ci < L.M; ++ci) {
+            const double* c = src + (size_t)L.cam_ext[ci] * 15;
+            for (int a = 0; a < 15; ++a)
+                if (!std::isfinite(c[a])) fail(DABA_E_INVAL, "camera %d has a non-finite entry", L.cam_ext[ci]);
+            if (!rotation_ok(c)) fail(DABA_E_INVAL, "camera %d: R is not a rotation", L.cam_ext[ci]);
+            cam_to_internal(c, s, &buf[(size_t)ci * kCamRec]);
         }
+        const size_t bytes = buf.size() * sizeof(double);
+        if (which == 0) {
+            upload(p.cams[k % 3], buf.data(), bytes, st);
+            upload(p.ccand[par][0], buf.data(), bytes, st);
+            upload(p.ccand[par][1], buf.data(), bytes, st);
+        } else {
+            upload(p.cams[(k + 2) % 3], buf.data(), bytes, st);
+        }
+        hipcheck(hipStreamSynchronize(st), "sync");
+    }
+    std::vector<double> pair(L.N * kLmPair);
+    for (int64_t li = 0; li < L.N; ++li) {
+        double* q = &pair[(size_t)li * kLmPair];
+        const int j = L.lm_ext[li];
+        for (int a = 0; a < 3; ++a) {
+            q[a] = lms[3 * (size_t)j + a];
+            q[4 + a] = lms_prev[3 * (size_t)j + a];
+            if (!std::isfinite(q[a]) || !std::isfinite(q[4 + a]))
+                fail(DABA_E_INVAL, "landmark %d has a non-finite entry", j);
+        }
+        long long beta = L.lpart[j];
+        std::memcpy(&q[3], &beta, sizeof beta);
+        q[7] = 0.0;
+    }
+    upload(p.lcp[par][0], pair.data(), pair.size() * sizeof(double), st);
+    upload(p.lcp[par][1], pair.data(), pair.size() * sizeof(double), st);
+    std::vector<float> pf;
+    if (h->opt.precision == DABA_FP32_MIXED) {
+        pf.resize(L.N * kLmPair);
+        for (int64_t li = 0; li < L.N; ++li) {
+            const double* q = &pair[(size_t)li * kLmPair];
+            float* fq = &pf[(size_t)li * kLmPair];
+            for (int a = 0; a < 3; ++a) {
+                fq[a] = (float)q[a];
+                fq[4 + a] = (float)q[4 + a];
+            }
+            int beta = L.lpart[L.lm_ext[li]];
+            std::memcpy(&fq[3], &beta, sizeof beta);
+            fq[7] = 0.0f;
+        }
+        upload(p.lcp32[par][0], pf.data(), pf.size() * sizeof(float), st);
+        upload(p.lcp32[par][1], pf.data(), pf.size() * sizeof(float), st);
+    }
+    hipcheck(launch_extrapolate_cams(p, k, st), "extrapolate");
+    DevState s0;
+    download(&s0, p.st, sizeof s0, st);
+    hipcheck(hipStreamSynchronize(st), "sync");
+    s0.decided = 1;
+    upload(p.st, &s0, sizeof s0, st);
+    hipcheck(hipStreamSynchronize(st), "sync");
+}
+
+// The current x^k and x^(k-1) in caller order and units; any output may be
+// empty.  Synchronizes.
+void read_point(daba_handle* h, std::vector<double>* cams, std::vector<double>* lms, std::vector<double>* cams_prev,
+                std::vector<double>* lms_prev) {
+    const Layout& L = h->L;
+    Params& p = h->p;
+    const double sc = p.scale;
+    const int k = (int)(h->k % 6);
+    hipStream_t st = h->stream;
+    for (int which = 0; which < 2; ++which) {
+        std::vector<double>* dst = which == 0 ? cams : cams_prev;
+        if (!dst) continue;
+        std::vector<double> buf(L.M * kCamRec);
+        download(buf.data(), which == 0 ? p.cams[k % 3] : p.cams[(k + 2) % 3], buf.size() * sizeof(double), st);
+        hipcheck(hipStreamSynchronize(st), "sync");
+        dst->assign(L.M * 15, 0.0);
+        for (int64_t ci = 0; ci < L.M; ++ci) cam_to_caller(&buf[(size_t)ci * kCamRec], sc, dst->data() + (size_t)L.cam_ext[ci] * 15);
     }
     if (lms || lms_prev) {
-        // read the current pair to keep the half that is not replaced
         std::vector<double> pair(L.N * kLmPair);
-        download(pair.data(), p.lpair[k & 1], pair.size() * sizeof(double), h->stream);
-        hipcheck(hipStreamSynchronize(h->stream), "sync");
+        download(pair.data(), cur_pair(h), pair.size() * sizeof(double), st);
+        hipcheck(hipStreamSynchronize(st), "sync");
+        if (lms) lms->assign(L.N * 3, 0.0);
+        if (lms_prev) lms_prev->assign(L.N * 3, 0.0);
         for (int64_t li = 0; li < L.N; ++li) {
-            double* q = &pair[(size_t)li * kLmPair];
-            int j = L.lm_ext[li];
-            if (lms)
-                for (int a = 0; a < 3; ++a) q[a] = lms[3 * (size_t)j + a];
-            if (lms_prev)
-                for (int a = 0; a < 3; ++a) q[4 + a] = lms_prev[3 * (size_t)j + a];
-            for (int a = 0; a < 3; ++a)
-                if (!std::isfinite(q[a]) || !std::isfinite(q[4 + a]))
-                    fail(DABA_E_INVAL, "landmark %d has a non-finite entry", j);
-            long long beta = L.lpart[j];
-            std::memcpy(&q[3], &beta, sizeof beta);
-            q[7] = 0.0;
-        }
-        upload(p.lpair[k & 1], pair.data(), pair.size() * sizeof(double), h->stream);
-        if (h->opt.precision == DABA_FP32_MIXED) {
-            std::vector<float> pf(L.N * kLmPair);
-            for (int64_t li = 0; li < L.N; ++li) {
-                const double* q = &pair[(size_t)li * kLmPair];
-                float* f = &pf[(size_t)li * kLmPair];
-                for (int a = 0; a < 3; ++a) {
-                    f[a] = (float)q[a];
-                    f[4 + a] = (float)q[4 + a];
-                }
-                int beta = L.lpart[L.lm_ext[li]];
-                std::memcpy(&f[3], &beta, sizeof beta);
-                f[7] = 0.0f;
+            const int j = L.lm_ext[li];
+            for (int a = 0; a < 3; ++a) {
+                if (lms) (*lms)[3 * (size_t)j + a] = pair[(size_t)li * kLmPair + a];
+                if (lms_prev) (*lms_prev)[3 * (size_t)j + a] = pair[(size_t)li * kLmPair + 4 + a];
             }
-            upload(p.lpair32[k & 1], pf.data(), pf.size() * sizeof(float), h->stream);
         }
-        hipcheck(hipStreamSynchronize(h->stream), "sync");
     }
 }
 
@@ -473,7 +532,7 @@ void init_metrics(daba_handle* h) {
     // eq. Fainit: F^a(-1) = E^a(x^0 | x^0) = sum of each pair's halves of F
     Params& p = h->p;
     const int k = (int)h->k;
-    hipcheck(launch_objective(p, p.cams[k % 3], p.lpair[k & 1], p.uv, h->d_obj, h->d_obj + h->L.S, h->stream),
+    hipcheck(launch_objective(p, p.cams[k % 3], cur_pair(h), p.uv, h->d_obj, h->d_obj + h->L.S, h->stream),
              "objective");
     std::vector<double> part(h->L.S + 1);
     download(part.data(), h->d_obj, part.size() * sizeof(double), h->stream);
@@ -601,8 +660,12 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         upload((void*)p.camblock_c1, L.camblock_c1.data(), L.camblock_c1.size() * sizeof(int), s);
         upload((void*)p.part_camblk, L.part_camblk.data(), (L.S + 1) * sizeof(int), s);
         upload((void*)p.part_lmblk, L.part_lmblk.data(), (L.S + 1) * sizeof(int), s);
+        upload((void*)p.lmblock_part, L.lmblock_part.data(), L.lmblock_part.size() * sizeof(int), s);
         upload((void*)p.cam_ext, L.cam_ext.data(), L.M * sizeof(int), s);
         upload((void*)p.lm_ext, L.lm_ext.data(), L.N * sizeof(int), s);
+        std::vector<int> lpart_int(L.N);
+        for (int64_t li = 0; li < L.N; ++li) lpart_int[li] = L.lpart[L.lm_ext[li]];
+        upload((void*)p.lm_part, lpart_int.data(), L.N * sizeof(int), s);
         hipcheck(hipStreamSynchronize(s), "sync");
         // state: x^(-1) = x^(0), s = 1, gamma = 0
         DevState st[2]{};
@@ -612,10 +675,11 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         upload(p.st, st, sizeof st, s);
         std::vector<double> zero(std::max<int64_t>(4 * L.S, 1), 0.0);
         upload(p.metrics, zero.data(), 4 * L.S * sizeof(double), s);
+        std::vector<int> zeroi(L.S, 0);
+        upload(p.restart, zeroi.data(), L.S * sizeof(int), s);
         hipcheck(hipStreamSynchronize(s), "sync");
         h->k = 0;
         write_point(h, prob->cameras, prob->landmarks, prob->cameras, prob->landmarks);
-        hipcheck(launch_extrapolate_cams(p, 0, s), "extrapolate");
         init_metrics(h);
         // capture the replayed period now, so that no later call pays for it
         ensure_period_graph(h);
@@ -632,17 +696,17 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
     }
 }
 
-// One iteration on stream s; ev (optional, 4 events) brackets the observation
-// pass, the entity solves, and the restart test with the selection.
+// One iteration on stream s: the restart test of the previous iteration (one
+// block), the observation pass, the entity solves; ev (optional, 3 events)
+// brackets the first two together and the entity solves.
 static void launch_iteration(daba_handle* h, int k, hipStream_t s, hipEvent_t* ev = nullptr) {
     const Params& p = h->p;
     if (ev) hipcheck(hipEventRecord(ev[0], s), "event");
+    hipcheck(launch_decide(p, k, s), "k_decide");
     hipcheck(launch_obs_pass(p, k, s), "k_obs");
     if (ev) hipcheck(hipEventRecord(ev[1], s), "event");
     hipcheck(launch_entity(p, k, s), "k_entity");
     if (ev) hipcheck(hipEventRecord(ev[2], s), "event");
-    hipcheck(launch_decide_select(p, k, s), "k_decide_select");
-    if (ev) hipcheck(hipEventRecord(ev[3], s), "event");
 }
 
 // Captures iterations with k mod 6 = 0..5 once; replaying the graph runs one
@@ -669,21 +733,23 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     // per-kernel timing: events for up to kPool iterations, drained in batches
     constexpr int kPool = 64;
     std::vector<hipEvent_t> ev;
+    hipEvent_t fin[2] = {nullptr, nullptr};
     int pooled = 0;
     auto drain = [&]() {
         if (pooled == 0) return;
-        hipcheck(hipEventSynchronize(ev[4 * (pooled - 1) + 3]), "event sync");
+        hipcheck(hipEventSynchronize(ev[3 * (pooled - 1) + 2]), "event sync");
         for (int q = 0; q < pooled; ++q)
-            for (int e = 0; e < 3; ++e) {
+            for (int e = 0; e < 2; ++e) {
                 float t = 0.f;
-                hipcheck(hipEventElapsedTime(&t, ev[4 * q + e], ev[4 * q + e + 1]), "elapsed");
+                hipcheck(hipEventElapsedTime(&t, ev[3 * q + e], ev[3 * q + e + 1]), "elapsed");
                 ms[e] += t;
             }
         pooled = 0;
     };
     if (ms) {
-        ev.resize(4 * kPool);
+        ev.resize(3 * kPool);
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
+        for (auto& e : fin) hipcheck(hipEventCreate(&e), "hipEventCreate");
         for (int e = 0; e < 3; ++e) ms[e] = 0.0;
     }
     int done = 0;
@@ -697,9 +763,19 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
                 continue;
             }
             const int k = (int)(h->k % 6);
-            launch_iteration(h, k, s, ms ? &ev[4 * pooled] : nullptr);
+            launch_iteration(h, k, s, ms ? &ev[3 * pooled] : nullptr);
             if (ms && ++pooled == kPool) drain();
             h->k++;
+        }
+        // the restart test of the chunk's last iteration, and x^k stored plainly
+        if (ms) hipcheck(hipEventRecord(fin[0], s), "event");
+        hipcheck(launch_finalize(p, (int)(h->k % 6), s), "k_finalize");
+        if (ms) {
+            hipcheck(hipEventRecord(fin[1], s), "event");
+            hipcheck(hipEventSynchronize(fin[1]), "event sync");
+            float t = 0.f;
+            hipcheck(hipEventElapsedTime(&t, fin[0], fin[1]), "elapsed");
+            ms[2] += t;
         }
         if (F_trace) {
             // entries k0+done+1 .. k0+done+chunk-1 were written by this chunk
@@ -715,7 +791,7 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     if (F_trace && n > 0) {
         // F(x^(k0+n)): one objective pass at the new iterate
         const int k = (int)(h->k % 6);
-        hipcheck(launch_objective(p, p.cams[k % 3], p.lpair[k & 1], p.uv, nullptr, h->d_obj, s), "objective");
+        hipcheck(launch_objective(p, p.cams[k % 3], cur_pair(h), p.uv, nullptr, h->d_obj, s), "objective");
         double F;
         download(&F, h->d_obj, sizeof F, s);
         sync_and_check(h);
@@ -723,7 +799,8 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     }
     if (ms) {
         drain();
-        for (auto& e : ev) hipEventDestroy(e);
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        for (auto& e : fin) (void)hipEventDestroy(e);
     }
     return DABA_OK;
 }
@@ -757,7 +834,7 @@ static void prepare_point(daba_handle* h, const double* cams, const double* lms,
     hipStream_t s = h->stream;
     if (!cams && !lms && !uv) {
         *pc = p.cams[k % 3];
-        *pl = p.lpair[k & 1];
+        *pl = cur_pair(h);
         *pu = p.uv;
         return;
     }
@@ -765,7 +842,7 @@ static void prepare_point(daba_handle* h, const double* cams, const double* lms,
         hipcheck(hipMemcpyAsync(p.tmp_cams, p.cams[k % 3], h->L.M * kCamRec * sizeof(double), hipMemcpyDeviceToDevice, s),
                  "copy");
     if (!lms)
-        hipcheck(hipMemcpyAsync(p.tmp_lpair, p.lpair[k & 1], h->L.N * kLmPair * sizeof(double),
+        hipcheck(hipMemcpyAsync(p.tmp_lpair, cur_pair(h), h->L.N * kLmPair * sizeof(double),
                                 hipMemcpyDeviceToDevice, s), "copy");
     if (!uv && h->L.K > 0)
         hipcheck(hipMemcpyAsync(p.tmp_uv, p.uv, h->L.K * sizeof(double2), hipMemcpyDeviceToDevice, s), "copy");
@@ -817,27 +894,13 @@ int daba_get_state(daba_handle* h, double* cams, double* lms, double* cams_prev,
         const int64_t k = hh->k;
         hipStream_t s = hh->stream;
         sync_and_check(hh);
-        const double sc = p.scale, s2 = sc * sc;
-        for (int which = 0; which < 2; ++which) {
-            double* dst = which == 0 ? cc->c : cc->cp;
-            if (!dst) continue;
-            std::vector<double> buf(L.M * kCamRec);
-            download(buf.data(), which == 0 ? p.cams[k % 3] : p.cams[(k + 2) % 3], buf.size() * sizeof(double), s);
-            hipcheck(hipStreamSynchronize(s), "sync");
-            for (int64_t ci = 0; ci < L.M; ++ci) cam_to_caller(&buf[(size_t)ci * kCamRec], sc, dst + (size_t)L.cam_ext[ci] * 15);
-        }
-        if (cc->l || cc->lp) {
-            std::vector<double> pair(L.N * kLmPair);
-            download(pair.data(), p.lpair[k & 1], pair.size() * sizeof(double), s);
-            hipcheck(hipStreamSynchronize(s), "sync");
-            for (int64_t li = 0; li < L.N; ++li) {
-                int j = L.lm_ext[li];
-                for (int a = 0; a < 3; ++a) {
-                    if (cc->l) cc->l[3 * (size_t)j + a] = pair[(size_t)li * kLmPair + a];
-                    if (cc->lp) cc->lp[3 * (size_t)j + a] = pair[(size_t)li * kLmPair + 4 + a];
-                }
-            }
-        }
+        const double s2 = p.scale * p.scale;
+        std::vector<double> vc, vl, vcp, vlp;
+        read_point(hh, cc->c ? &vc : nullptr, cc->l ? &vl : nullptr, cc->cp ? &vcp : nullptr, cc->lp ? &vlp : nullptr);
+        if (cc->c) std::memcpy(cc->c, vc.data(), vc.size() * sizeof(double));
+        if (cc->l) std::memcpy(cc->l, vl.data(), vl.size() * sizeof(double));
+        if (cc->cp) std::memcpy(cc->cp, vcp.data(), vcp.size() * sizeof(double));
+        if (cc->lp) std::memcpy(cc->lp, vlp.data(), vlp.size() * sizeof(double));
         if (cc->p4) {
             const int S = L.S;
             std::vector<double> a(S), b(S), c2(S), d(S);
@@ -873,53 +936,41 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
         C* cc = static_cast<C*>(v);
         Params& p = hh->p;
         hipStream_t s = hh->stream;
+        const Layout& L = hh->L;
         hipcheck(hipStreamSynchronize(s), "sync");
+        // the point as it is, with the parts the caller gives replaced
+        std::vector<double> vc, vl, vcp, vlp;
+        read_point(hh, &vc, &vl, &vcp, &vlp);
+        if (cc->c) std::memcpy(vc.data(), cc->c, vc.size() * sizeof(double));
+        if (cc->l) std::memcpy(vl.data(), cc->l, vl.size() * sizeof(double));
+        if (cc->cp) std::memcpy(vcp.data(), cc->cp, vcp.size() * sizeof(double));
+        if (cc->lp) std::memcpy(vlp.data(), cc->lp, vlp.size() * sizeof(double));
         if (cc->sc) {
+            if (!(cc->sc[0] >= 1.0) || cc->sc[1] < 0) fail(DABA_E_INVAL, "bad scalars (s >= 1, k >= 0)");
+            const int64_t knew = (int64_t)cc->sc[1];
             DevState sts[2];
             download(sts, p.st, sizeof sts, s);
             hipcheck(hipStreamSynchronize(s), "sync");
-            if (!(cc->sc[0] >= 1.0) || cc->sc[1] < 0) fail(DABA_E_INVAL, "bad scalars (s >= 1, k >= 0)");
-            DevState st = sts[((int64_t)cc->sc[1]) & 1];
+            DevState st = sts[knew & 1];
             st.s = cc->sc[0];
             const double s1 = (std::sqrt(4.0 * st.s * st.s + 1.0) + 1.0) / 2.0;
             st.gamma = p.accelerate ? (st.s - 1.0) / s1 : 0.0;
-            // keep the buffer rotation: move the current point to the new
-            // counter's buffers
-            const int64_t knew = (int64_t)cc->sc[1];
-            if (knew % 6 != hh->k % 6) {
-                const Layout& L = hh->L;
-                const int ko = (int)(hh->k % 6), kn = (int)(knew % 6);
-                std::vector<double> c0(L.M * kCamRec), c1(L.M * kCamRec), pr(L.N * kLmPair);
-                download(c0.data(), p.cams[ko % 3], c0.size() * sizeof(double), s);
-                download(c1.data(), p.cams[(ko + 2) % 3], c1.size() * sizeof(double), s);
-                download(pr.data(), p.lpair[ko & 1], pr.size() * sizeof(double), s);
-                hipcheck(hipStreamSynchronize(s), "sync");
-                upload(p.cams[kn % 3], c0.data(), c0.size() * sizeof(double), s);
-                upload(p.cams[(kn + 2) % 3], c1.data(), c1.size() * sizeof(double), s);
-                upload(p.lpair[kn & 1], pr.data(), pr.size() * sizeof(double), s);
-                if ((kn & 1) != (ko & 1)) {
-                    // the restart bookkeeping follows the counter's parity slot
-                    const int S = L.S;
-                    for (double* arr : {p.Fbar, p.E, p.EE, p.Fprev})
-                        hipcheck(hipMemcpyAsync(arr + (size_t)(kn & 1) * S, arr + (size_t)(ko & 1) * S,
-                                                S * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
-                }
-                if (p.fp32) {
-                    std::vector<float> pf(L.N * kLmPair);
-                    download(pf.data(), p.lpair32[ko & 1], pf.size() * sizeof(float), s);
-                    hipcheck(hipStreamSynchronize(s), "sync");
-                    upload(p.lpair32[kn & 1], pf.data(), pf.size() * sizeof(float), s);
-                }
-                hipcheck(hipStreamSynchronize(s), "sync");
+            st.k = knew;
+            if ((knew & 1) != (hh->k & 1)) {
+                // the restart bookkeeping follows the counter's parity slot
+                const int S = L.S;
+                for (double* arr : {p.Fbar, p.E, p.EE, p.Fprev})
+                    hipcheck(hipMemcpyAsync(arr + (size_t)(knew & 1) * S, arr + (size_t)(hh->k & 1) * S,
+                                            S * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
             }
             hh->k = knew;
-            st.k = knew;
+            if ((knew & 1) == 0) st.decided = sts[0].decided, st.err = sts[0].err;
             upload(p.st + (knew & 1), &st, sizeof st, s);
             hipcheck(hipStreamSynchronize(s), "sync");
         }
-        write_point(hh, cc->c, cc->l, cc->cp, cc->lp);
+        write_point(hh, vc.data(), vl.data(), vcp.data(), vlp.data());
         if (cc->p4) {
-            const int S = hh->L.S;
+            const int S = L.S;
             const double s2 = p.scale * p.scale;
             std::vector<double> a(S), b(S), c2(S), d(S);
             for (int q = 0; q < S; ++q) {
@@ -933,9 +984,8 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
             upload(p.E + slot, b.data(), S * sizeof(double), s);
             upload(p.EE + slot, c2.data(), S * sizeof(double), s);
             upload(p.Fprev + slot, d.data(), S * sizeof(double), s);
+            hipcheck(hipStreamSynchronize(s), "sync");
         }
-        hipcheck(launch_extrapolate_cams(p, (int)(hh->k % 6), s), "extrapolate");
-        hipcheck(hipStreamSynchronize(s), "sync");
         return DABA_OK;
     }, &c);
 }

@@ -6,11 +6,15 @@
 //    landmark id): pixel uv (double2 / float2, internal units), internal
 //    landmark id, landmark-side slot, original index;
 //  * cameras in partition-major order, one 128-byte record each
-//    (R row-major 9 | t 3 | d 3 | pad), three rotating generations
-//    x^(k-1), x^k, x^(k+1) plus the extrapolated x-bar^k and two candidates;
-//  * landmarks in (partition, track length) order; a 64-byte pair record
-//    (l^k xyz, partition id, l^(k-1) xyz, pad) double-buffered, an FP32 copy,
-//    and two candidate buffers;
+//    (R row-major 9 | t 3 | d 3 | pad): three rotating generations of the
+//    chosen iterate, and the two candidates of the last iteration (plain MM
+//    and accelerated) with the extrapolation each would give;
+//  * landmarks in (partition, track length) order; the two candidates of the
+//    last iteration as 64-byte pair records (candidate xyz, partition id,
+//    l^k xyz, pad), double-buffered by iteration parity, with FP32 copies;
+//  * the landmark index of an observation carries its landmark's partition
+//    in the top bits (kLmBits), so a fetch can pick the partition's
+//    candidate without reading the record first;
 //  * landmark-side per-observation records at their slot: groups of up to 64
 //    landmarks with one track length D are stored observation-major
 //    (slot = base + k * n + lane), so the landmark pass reads them coalesced.
@@ -32,16 +36,19 @@ constexpr int kLmPair = 8;           // doubles per landmark pair record
 constexpr int kCamBlock = 128;       // cameras per block of the camera solve
 constexpr int kLmWaves = 4;          // groups per block of the landmark pass
 constexpr int kMaxPart = 64;
+constexpr int kLmBits = 26;              // landmark index bits in obs_lm (partition above)
+constexpr int kLmMask = (1 << kLmBits) - 1;
 
-// Two slots, by iteration parity: iteration k reads slot k & 1 and writes
-// slot (k + 1) & 1.  The sticky error code lives in slot 0.
+// Two slots, by iteration parity: the restart test of iteration k - 1 reads
+// slot (k - 1) & 1 and writes slot k & 1, which iteration k then uses.  The
+// sticky error code and the decided flag live in slot 0.
 struct DevState {
     double s;        // s^(k)
     double gamma;    // gamma^(k) used by iteration k
-    double F;        // F(x^(k-1)) computed by iteration k - 1 (internal units)
+    double F;        // F(x^(k-1)) (internal units)
     int64_t k;
     int32_t err;     // sticky error code (0 = none), slot 0 only
-    int32_t pad;
+    int32_t decided; // slot 0: 1 if the restart test of the last iteration is stored
 };
 
 // Everything a kernel needs, passed by value.
@@ -80,17 +87,19 @@ struct Params {
     const int* camblock_c1;
     const int* part_camblk;   // [S+1] camera blocks of each partition
     const int* part_lmblk;    // [S+1] landmark blocks of each partition
+    const int* lmblock_part;  // [nLmBlocks] partition of each landmark block
     const int* cam_ext;       // internal -> caller camera index
     const int* lm_ext;        // internal -> caller landmark index
+    const int* lm_part;       // [N] partition of each internal landmark
 
-    // state
-    double* cams[3];
-    double* cam_bar;
-    double* cam_cand[2];      // 0: plain MM, 1: accelerated
-    double* cam_bar_cand[2];  // x-bar^(k+1) if candidate 0 / 1 is chosen
-    double* lpair[2];
-    float* lpair32[2];
-    double* lcand[2];
+    // state.  Iteration k reads the candidates of parity (k + 1) & 1 (those
+    // of iteration k - 1, chosen by its restart test) and writes parity k & 1.
+    double* cams[3];          // chosen x^k in generation k % 3
+    double* ccand[2][2];      // [parity][0: plain MM, 1: accelerated] camera candidates
+    double* cbar[2][2];       // x-bar the next iteration uses if that candidate is chosen
+    double* lcp[2][2];        // [parity][candidate] landmark pair records
+    float* lcp32[2][2];
+    int* restart;             // [S] restart test of the last decided iteration
     double* rec;              // [K * 8] landmark-side records at their slots
     float* rec32;             // [K * 8] the same in FP32 (mixed precision)
     double* tile_vals;        // [T * kTileVals]
@@ -119,12 +128,17 @@ struct Params {
 // k mod 2 the landmark pair buffer.
 hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s);
 hipError_t launch_entity(const Params& p, int k, hipStream_t s);  // camera and landmark subproblems
-// Restart decision and selection (rolls x^k -> x^(k+1), extrapolates cameras).
-hipError_t launch_decide_select(const Params& p, int k, hipStream_t s);
+// Restart test of iteration k - 1 unless already stored (one block).
+hipError_t launch_decide(const Params& p, int k, hipStream_t s);
+// Restart test of iteration k - 1 and the choice of its candidates, written
+// into both candidate slots and the camera generation k % 3 (a call
+// boundary: afterwards every buffer holds x^k).
+hipError_t launch_finalize(const Params& p, int k, hipStream_t s);
 // Objective shares at (cams, lpair, uv): tile F shares and bins -> Fsh^a and F.
 hipError_t launch_objective(const Params& p, const double* cams, const double* lpair, const double2* uv,
                             double* part_out /*[S]*/, double* F_out /*[1]*/, hipStream_t s);
-// x-bar^k for cameras from (x^k, x^(k-1)) with gamma read from the state.
+// Both x-bar candidates of parity (k + 1) & 1 from (x^k, x^(k-1)) with gamma^(k)
+// read from the state.
 hipError_t launch_extrapolate_cams(const Params& p, int k, hipStream_t s);
 // Caller arrays -> internal scratch (units and order).
 hipError_t launch_import_point(const Params& p, const double* cams, const double* lms, const double* uv,

@@ -3,22 +3,25 @@
 // camera and per landmark, and camera partitions act as the devices of the
 // adaptive restart (Sec. V).
 //
-// Per iteration k (r = k mod 3 picks the camera generation, k mod 2 the
-// landmark pair buffer):
-//   k_obs      one wave per camera tile: evaluates every observation at x^k,
-//              at the extrapolated x-bar^k and at x^(k-1); accumulates the
-//              camera moments of both surrogates (FP64), the F share and the
-//              surrogate-gap share; bins the landmark-side shares per
-//              partition; writes the landmark-side record to its slot.
-//   k_entity   camera subproblems (Levenberg-Marquardt on the moments) and,
+// Per iteration k (k mod 3 picks the camera generation, k mod 2 the parity
+// of the candidate buffers), three launches:
+//   k_decide   (one block) the restart test of iteration k - 1 (eq. Fak,
+//              lFak, Eak), which picks each partition's candidate (eq.
+//              update_amm or update_mm) as x^k;
+//   k_obs      one wave per camera tile evaluates every observation at x^k,
+//              taken from that candidate, at the extrapolated
+//              x-bar^k and at x^(k-1); accumulates the camera moments of both
+//              surrogates (FP64), the F share and the surrogate-gap share;
+//              bins the landmark-side shares per partition; writes the
+//              landmark-side record to its slot.
+//   k_entity   camera subproblems (Levenberg-Marquardt on the moments, and
+//              the next extrapolation of each candidate, eq. nesterov_x) and,
 //              in other blocks of the same launch, landmark subproblems (one
 //              lane per landmark: the records k_obs wrote at its slots, then
 //              the closed form) and the column sums of the partition bins.
-//   k_decide_select
-//              per-partition restart metrics and test (eq. Fak, lFak, Eak),
-//              computed in every block; then picks each partition's
-//              candidate, rolls the iterates and extrapolates the cameras for
-//              the next iteration.
+// At the end of a call k_finalize takes the last restart test and writes
+// the chosen candidates everywhere, so that between calls x^k is stored
+// plainly.
 //
 // Numerics.  Camera statistics are taken about the linearization point y
 // (Appendix-style moment form): with z = (ux, uy, 1, |u|^2, |u|^4, lambda),
@@ -228,12 +231,17 @@ __device__ __forceinline__ void load_uv<float>(const Params& p, int o, float& ux
     uy = u.y;
 }
 
+// candidate pair records read by iteration k (written by iteration k - 1)
 template <typename R>
-__device__ __forceinline__ const R* pair_base(const Params& p, int k);
+__device__ __forceinline__ const R* pair_base(const Params& p, int k, int cand);
 template <>
-__device__ __forceinline__ const double* pair_base<double>(const Params& p, int k) { return p.lpair[k & 1]; }
+__device__ __forceinline__ const double* pair_base<double>(const Params& p, int k, int cand) {
+    return p.lcp[(k + 1) & 1][cand];
+}
 template <>
-__device__ __forceinline__ const float* pair_base<float>(const Params& p, int k) { return p.lpair32[k & 1]; }
+__device__ __forceinline__ const float* pair_base<float>(const Params& p, int k, int cand) {
+    return p.lcp32[(k + 1) & 1][cand];
+}
 
 template <typename R>
 __device__ __forceinline__ R* rec_base(const Params& p);
@@ -277,6 +285,125 @@ __device__ __forceinline__ void flush_run(int key, double& r0, double& r1, int l
     r1 = 0.0;
 }
 
+// --------------------------------------------------- restart test (Sec. V)
+
+// eq. nesterov_scalar: s^(k+1) from s^(k), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
+__device__ __forceinline__ double next_gamma(const Params& p, double s, double* s1_out) {
+    const double s1 = (sqrt(4.0 * s * s + 1.0) + 1.0) / 2.0;
+    const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
+    *s1_out = s1;
+    return p.accelerate ? (s1 - 1.0) / s2 : 0.0;
+}
+
+// Restart test of iteration kp (eq. Fak, lFak, Eak) for every partition, by
+// one block of 256 threads: each wave sums two partitions at a time over the
+// block sums k_entity left (lanes strided, then a wave reduction) and its
+// lane 0 takes the test.  Every caller sums the same values in the same
+// order, so every block that takes the test gets the same answer.  The
+// writer stores the bookkeeping of slot (kp + 1) & 1, the metrics, the flags
+// and the next Nesterov state.  Flags (1: the partition restarts, i.e. keeps
+// the plain MM candidate) and F shares go to s_rs / s_Fsh.  kp may be -1.
+__device__ void part_sums(const Params& p, int a, int lane, double* c, double* l) {
+    for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
+        const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)q * 4);
+        c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
+    }
+    for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
+        const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)q * 2);
+        l[0] += v.x; l[1] += v.y;
+    }
+}
+
+__device__ void test_one(const Params& p, int kp, bool writer, int a, const double* c, const double* l, int* s_rs,
+                         double* s_Fsh) {
+    const int S = p.S;
+    const int cur = (kp & 1) * S, nxt = ((kp + 1) & 1) * S;
+    // E^a(x^k | x^k): each pair's F split in halves between its sides
+    const double Fsh = c[2] + p.colsum[a];
+    // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
+    const double V = Fsh + c[3] + p.colsum[S + a];
+    const double Fk = p.E[cur + a] + V - p.EE[cur + a];               // eq. Fak
+    const double Fb = (1.0 - p.eta) * p.Fbar[cur + a] + p.eta * Fk;   // eq. lFak
+    const double dmm = c[0] + l[0], dacc = c[1] + l[1];
+    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                     // eq. Eak test
+    if (p.accelerate && (p.flags & 1)) rs = 0;
+    if (p.accelerate && (p.flags & 2)) rs = 1;
+    const double dch = rs ? dmm : dacc;
+    s_rs[a] = rs;
+    s_Fsh[a] = Fsh;
+    if (writer) {
+        p.Fprev[nxt + a] = Fk;
+        p.Fbar[nxt + a] = Fb;
+        p.E[nxt + a] = Fk + dch;
+        p.EE[nxt + a] = Fsh + dch;
+        p.metrics[4 * a + 0] = Fk;
+        p.metrics[4 * a + 1] = Fb;
+        p.metrics[4 * a + 2] = Fk + dch;
+        p.metrics[4 * a + 3] = (double)rs;
+        p.restart[a] = rs;
+    }
+}
+
+__device__ void restart_test_block(const Params& p, int kp, bool writer, int* s_rs, double* s_Fsh) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int S = p.S;
+    for (int a0 = wv; a0 < S; a0 += 8) {
+        const int a1 = a0 + 4;
+        double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
+        part_sums(p, a0, lane, c0, l0);
+        if (a1 < S) part_sums(p, a1, lane, c1, l1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c0[q] = wave_sum(c0[q]);
+            c1[q] = wave_sum(c1[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            l0[q] = wave_sum(l0[q]);
+            l1[q] = wave_sum(l1[q]);
+        }
+        if (lane == 0) {
+            test_one(p, kp, writer, a0, c0, l0, s_rs, s_Fsh);
+            if (a1 < S) test_one(p, kp, writer, a1, c1, l1, s_rs, s_Fsh);
+        }
+    }
+    __syncthreads();
+    if (writer && threadIdx.x == 0) {
+        double F = 0.0;
+        for (int a = 0; a < S; ++a) F += s_Fsh[a];
+        const DevState& sc = p.st[kp & 1];
+        double s1;
+        const double gam = next_gamma(p, sc.s, &s1);
+        if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
+        const int64_t kk = sc.k;
+        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
+        DevState& sn = p.st[(kp + 1) & 1];
+        sn.F = F;
+        sn.s = s1;
+        sn.gamma = gam;
+        sn.k = kk + 1;
+    }
+}
+
+// Start of iteration k: the restart test of iteration k - 1, unless it is
+// already stored (after daba_create, daba_set_state or a previous call).
+// One block.
+__global__ __launch_bounds__(256) void k_decide(Params p, int k) {
+    __shared__ int s_rs[kMaxPart];
+    __shared__ double s_Fsh[kMaxPart];
+    if (p.st[0].decided) return;
+    restart_test_block(p, k - 1, true, s_rs, s_Fsh);
+}
+
+// The restart flags of iteration k - 1 as a bit mask (stored by k_decide).
+__device__ __forceinline__ uint64_t restart_mask(const Params& p) {
+    const int lane = threadIdx.x & (kWave - 1);
+    return __ballot(lane < p.S && p.restart[lane] != 0);
+}
+// candidate chosen for partition a: 0 (plain MM) on restart, else 1
+__device__ __forceinline__ int chosen(uint64_t restart, int a) { return ((restart >> a) & 1) ? 0 : 1; }
+
 // ------------------------------------------------------- observation pass
 
 constexpr int kAcc = 78;   // 2 x 38 moments + F share + gap share
@@ -301,6 +428,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
 #pragma unroll
     for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
 
+    const uint64_t rmask = restart_mask(p);
     int beg = 0, end = 0, ci = 0, alpha = 0;
     if (active) {
         ci = uniform_int(p.tile_cam[t]);
@@ -308,20 +436,22 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
         end = uniform_int(p.tile_end[t]);
         alpha = uniform_int(p.cam_part[ci]);
     }
-    const CamT<R> ck = load_cam<R>(p.cams[k % 3] + (size_t)ci * kCamRec);
+    const int cc = chosen(rmask, alpha);
+    const CamT<R> ck = load_cam<R>(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
     const CamT<R> cp = load_cam<R>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
     CamT<R> cb;
-    if constexpr (ACC) cb = load_cam<R>(p.cam_bar + (size_t)ci * kCamRec);
+    if constexpr (ACC) cb = load_cam<R>(p.cbar[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
     const R gam = ACC ? (R)p.st[k & 1].gamma : (R)0;
     const R delta = (R)p.delta;
-    const R* __restrict__ pairs = pair_base<R>(p, k);
+    const R* __restrict__ pairs0 = pair_base<R>(p, k, 0);
+    const R* __restrict__ pairs1 = pair_base<R>(p, k, 1);
     R* __restrict__ rec = rec_base<R>(p);
     bool bad = false;
     int run_key = -1;       // wave-uniform landmark partition of the open run
     double run0 = 0.0, run1 = 0.0;
     __syncthreads();
 
-    int li_next = beg + lane < end ? p.obs_lm[beg + lane] : 0;
+    int li_next = beg + lane < end ? p.obs_lm[beg + lane] : 0;  // with the partition in the top bits
     for (int base = beg; base < end; base += kWave) {
         const int o = base + lane;
         const bool on = o < end;
@@ -335,7 +465,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
             R ux, uy;
             load_uv<R>(p, o, ux, uy);
             const int slot = p.obs_slot[o];
-            const LmRead<R> L = read_pair(pairs, li);
+            const LmRead<R> L = read_pair(chosen(rmask, li >> kLmBits) ? pairs1 : pairs0, li & kLmMask);
             const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
             const R r6u = r4u * r2u, r8u = r4u * r4u;
 
@@ -504,6 +634,7 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
 #pragma unroll
     for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
 
+    const uint64_t restart = restart_mask(p);
     int beg = 0, end = 0, ci = 0, alpha = 0;
     if (active) {
         ci = uniform_int(p.tile_cam[t]);
@@ -511,13 +642,17 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         end = uniform_int(p.tile_end[t]);
         alpha = uniform_int(p.cam_part[ci]);
     }
-    const CamT<double> ck = load_cam<double>(p.cams[k % 3] + (size_t)ci * kCamRec);
+    const int cc = chosen(restart, alpha);
+    const CamT<double> ck = load_cam<double>(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
     const CamT<double> cp = load_cam<double>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
     CamT<double> cb;
-    if constexpr (ACC) cb = load_cam<double>(p.cam_bar + (size_t)ci * kCamRec);
+    if constexpr (ACC) cb = load_cam<double>(p.cbar[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
     const double gam = ACC ? p.st[k & 1].gamma : 0.0;
     const double delta = p.delta;
-    const char* __restrict__ pbase = reinterpret_cast<const char*>(p.lpair[k & 1]);
+    // both candidate buffers of a parity are one allocation: candidate 1
+    // follows candidate 0 after N records
+    const char* __restrict__ pbase = reinterpret_cast<const char*>(p.lcp[(k + 1) & 1][0]);
+    const uint64_t cand_stride = (uint64_t)p.N * (kLmPair * 8);
     double* __restrict__ rec = p.rec;
     bool bad = false;
     int run_key = -1;
@@ -542,8 +677,11 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         const int ln = opaque_lane(), quad = ln >> 2, qc = ln & 3;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const unsigned li = (unsigned)__shfl(li_ahead, 16 * i + quad);
-            dma16(pbase + (li * (unsigned)(kLmPair * 8) + 16u * qc), &D.pair[16 * i * kLmPair]);
+            const unsigned lp = (unsigned)__shfl(li_ahead, 16 * i + quad);
+            const unsigned li = lp & kLmMask;
+            const uint64_t off = (uint64_t)chosen(restart, (int)(lp >> kLmBits)) * cand_stride +
+                                 (uint64_t)li * (kLmPair * 8) + 16u * qc;
+            dma16(pbase + off, &D.pair[16 * i * kLmPair]);
         }
         const unsigned o = (unsigned)min(beg + kWave * st + ln, last);
         dma16(reinterpret_cast<const char*>(p.uv) + 16u * o, &D.uv[0]);
@@ -1148,13 +1286,6 @@ __device__ void extrapolate_cam(const double* cn, const double* co, double gam, 
     out[15] = 0.0;
 }
 
-// eq. nesterov_scalar: s^(k+1) from s^(k), and gamma^(k+1) = (s^(k+1) - 1) / s^(k+2)
-__device__ __forceinline__ double next_gamma(const Params& p, double s, double* s1_out) {
-    const double s1 = (sqrt(4.0 * s * s + 1.0) + 1.0) / 2.0;
-    const double s2 = (sqrt(4.0 * s1 * s1 + 1.0) + 1.0) / 2.0;
-    *s1_out = s1;
-    return p.accelerate ? (s1 - 1.0) / s2 : 0.0;
-}
 
 // Camera subproblems of one block of <= 128 cameras in one partition:
 // threads [0,128) solve the plain surrogate, [128,256) the accelerated one.
@@ -1179,10 +1310,14 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, doubl
             f1 += tv[2 * kMom];
             f2 += tv[2 * kMom + 1];
         }
-        const CamD ck = load_camd(p.cams[k % 3] + (size_t)ci * kCamRec);
-        const CamD y = surr == 0 ? ck : load_camd(p.cam_bar + (size_t)ci * kCamRec);
+        // x^k and x-bar^k: the candidates of iteration k - 1 chosen by its
+        // restart test (stored by k_obs or by the previous call)
+        const int cc = p.restart[p.cam_part[ci]] ? 0 : 1;
+        const CamD ck = load_camd(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
+        if (surr == 0) store_camd(p.cams[k % 3] + (size_t)ci * kCamRec, ck);
+        const CamD y = surr == 0 ? ck : load_camd(p.cbar[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
         const CamD c = lm_camera(mom, y, xi, p.inner_steps);
-        store_camd(p.cam_cand[surr] + (size_t)ci * kCamRec, c);
+        store_camd(p.ccand[k & 1][surr] + (size_t)ci * kCamRec, c);
         if constexpr (ACC) {
             // the extrapolation the next iteration uses if this candidate is
             // chosen; gamma^(k+1) depends only on s^(k), so it is known now
@@ -1197,8 +1332,17 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, doubl
                 cn[12 + a] = c.d[a];
             }
             cn[15] = 0.0;
-            extrapolate_cam(cn, p.cams[k % 3] + (size_t)ci * kCamRec, gnext, cbar);
-            double* dst = p.cam_bar_cand[surr] + (size_t)ci * kCamRec;
+            double cko[16];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) cko[a] = ck.R[a];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cko[9 + a] = ck.t[a];
+                cko[12 + a] = ck.d[a];
+            }
+            cko[15] = 0.0;
+            extrapolate_cam(cn, cko, gnext, cbar);
+            double* dst = p.cbar[k & 1][surr] + (size_t)ci * kCamRec;
 #pragma unroll
             for (int a = 0; a < 16; ++a) dst[a] = cbar[a];
         }
@@ -1270,6 +1414,21 @@ __device__ __forceinline__ void sum_records(const RT* __restrict__ rec, int64_t 
     }
 }
 
+// Candidate pair record (l^(k+1) candidate, partition id, l^k) of iteration k.
+__device__ __forceinline__ void write_cand_pair(const Params& p, int k, int cand, int li, const double* ln,
+                                                double beta_bits, const double* lk) {
+    double2* q = reinterpret_cast<double2*>(p.lcp[k & 1][cand] + (size_t)li * kLmPair);
+    q[0] = make_double2(ln[0], ln[1]);
+    q[1] = make_double2(ln[2], beta_bits);
+    q[2] = make_double2(lk[0], lk[1]);
+    q[3] = make_double2(lk[2], 0.0);
+    if (p.fp32) {
+        float4* f = reinterpret_cast<float4*>(p.lcp32[k & 1][cand] + (size_t)li * kLmPair);
+        f[0] = make_float4((float)ln[0], (float)ln[1], (float)ln[2], __int_as_float((int)__double_as_longlong(beta_bits)));
+        f[1] = make_float4((float)lk[0], (float)lk[1], (float)lk[2], 0.0f);
+    }
+}
+
 // One launch, three kinds of blocks: camera subproblems, landmark subproblems
 // (one wave per group of landmarks with equal track length), and column sums
 // of the per-tile partition bins.  The roles are independent, so the camera
@@ -1298,7 +1457,11 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
         return;
     }
     // ---- landmark subproblems: one wave per group of equal track length
+    if (blockIdx.x == (unsigned)p.nCamBlocks && threadIdx.x == 0) p.st[0].decided = 0;
     const int g = p.lmblock_g0[lb] + wv;
+    // l^k and l^(k-1): the candidate of iteration k - 1 chosen for this
+    // block's partition
+    const int lcc = p.restart[p.lmblock_part[lb]] ? 0 : 1;
     double dmm = 0.0, dacc = 0.0;
     if (g < p.lmblock_g1[lb]) {
         const int n = p.group_n[g], D = p.group_deg[g];
@@ -1307,7 +1470,7 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
         if (lane < n) {
             double W0 = 0, V0[3] = {0, 0, 0}, W1 = 0, V1[3] = {0, 0, 0};
             sum_records<RT, ACC>(rec_base<RT>(p), base, n, lane, D, W0, V0, W1, V1);
-            const LmRead<double> L = read_pair(p.lpair[k & 1], li);
+            const LmRead<double> L = read_pair(p.lcp[(k + 1) & 1][lcc], li);
             double dl[3], nm = 0.0, dv = 0.0;
             const double den0 = 2.0 * W0 + xi;
 #pragma unroll
@@ -1317,24 +1480,23 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
                 dv += dl[a] * V0[a];
             }
             dmm = (W0 + 0.5 * xi) * nm - dv;
-            double* cm = p.lcand[0] + (size_t)li * 4;
-            cm[0] = L.lk[0] + dl[0];
-            cm[1] = L.lk[1] + dl[1];
-            cm[2] = L.lk[2] + dl[2];
+            const double beta_bits = __longlong_as_double((long long)L.beta);
+            const double lm[3] = {L.lk[0] + dl[0], L.lk[1] + dl[1], L.lk[2] + dl[2]};
+            write_cand_pair(p, k, 0, li, lm, beta_bits, L.lk);
             if (ACC) {
                 const double gam = p.st[k & 1].gamma;
                 const double den1 = 2.0 * W1 + xi;
-                double da[3], na = 0.0, va = 0.0;
+                double la[3], na = 0.0, va = 0.0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
-                    double la = lbar + V1[a] / den1;
-                    p.lcand[1][(size_t)li * 4 + a] = la;
-                    da[a] = la - L.lk[a];
-                    na += da[a] * da[a];
-                    va += da[a] * V0[a];
+                    la[a] = lbar + V1[a] / den1;
+                    const double da = la[a] - L.lk[a];
+                    na += da * da;
+                    va += da * V0[a];
                 }
                 dacc = (W0 + 0.5 * xi) * na - va;
+                write_cand_pair(p, k, 1, li, la, beta_bits, L.lk);
             }
         }
     }
@@ -1354,176 +1516,61 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
 
 // ------------------------------------------------------- select and roll
 
-// Per-partition restart metrics and test (eq. Fak, lFak, Eak) from the
-// block sums of k_entity, for all S partitions; every block of the selection
-// computes them (in the same order, so identically) and block 0 stores them.
-// The bookkeeping is double-buffered by iteration parity: iteration k reads
-// slot k & 1 and writes slot (k + 1) & 1, so no block can see a half-updated
-// state.  (One decision kernel ahead of the selection would cost a launch; a
-// last-block-done decision inside k_entity would need a device-scope release
-// fence in every block, which writes back each XCD's whole L2.)
-struct DecideLds {
-    int camblk[kMaxPart + 1], lmblk[kMaxPart + 1];  // block ranges of each partition
-    double E[kMaxPart], EE[kMaxPart], Fbar[kMaxPart], col0[kMaxPart], col1[kMaxPart];
-    int rs[kMaxPart];
-    double Fsh[kMaxPart];
-};
-
-// Sums of the camera-block and landmark-block values of partition a (lane
-// partials; the caller reduces over the wave).
-__device__ __forceinline__ void part_sums(const Params& p, const DecideLds& d, int a, int lane, double* c, double* l) {
-    for (int q = d.camblk[a] + lane; q < d.camblk[a + 1]; q += kWave) {
-        const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)q * 4);
-        c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
-    }
-    for (int q = d.lmblk[a] + lane; q < d.lmblk[a + 1]; q += kWave) {
-        const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)q * 2);
-        l[0] += v.x; l[1] += v.y;
-    }
-}
-
-__device__ __forceinline__ void decide_one(const Params& p, int k, bool writer, DecideLds& d, int a,
-                                           const double* c, const double* l) {
-    const int S = p.S;
-    const int nxt = ((k + 1) & 1) * S;
-    // E^a(x^k | x^k): each pair's F split in halves between its sides
-    const double Fsh = c[2] + d.col0[a];
-    // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
-    const double V = Fsh + c[3] + d.col1[a];
-    const double Fk = d.E[a] + V - d.EE[a];                       // eq. Fak
-    const double Fb = (1.0 - p.eta) * d.Fbar[a] + p.eta * Fk;     // eq. lFak
-    const double dmm = c[0] + l[0], dacc = c[1] + l[1];
-    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                 // eq. Eak test
-    if (p.accelerate && (p.flags & 1)) rs = 0;
-    if (p.accelerate && (p.flags & 2)) rs = 1;
-    const double dch = rs ? dmm : dacc;
-    d.rs[a] = rs;
-    d.Fsh[a] = Fsh;
-    if (writer) {
-        p.Fprev[nxt + a] = Fk;
-        p.Fbar[nxt + a] = Fb;
-        p.E[nxt + a] = Fk + dch;
-        p.EE[nxt + a] = Fsh + dch;
-        p.metrics[4 * a + 0] = Fk;
-        p.metrics[4 * a + 1] = Fb;
-        p.metrics[4 * a + 2] = Fk + dch;
-        p.metrics[4 * a + 3] = (double)rs;
-    }
-}
-
-// Every block: bookkeeping into LDS in one round, then each wave sums two
-// partitions at a time (their loads in flight together).
-__device__ void decide(const Params& p, int k, bool writer, DecideLds& d) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int S = p.S;
-    const int cur = (k & 1) * S;
-    const int tid = threadIdx.x;
-    if (tid <= S) {
-        d.camblk[tid] = p.part_camblk[tid];
-        d.lmblk[tid] = p.part_lmblk[tid];
-    }
-    if (tid < S) {
-        d.E[tid] = p.E[cur + tid];
-        d.EE[tid] = p.EE[cur + tid];
-        d.Fbar[tid] = p.Fbar[cur + tid];
-        d.col0[tid] = p.colsum[tid];
-        d.col1[tid] = p.colsum[S + tid];
-    }
-    __syncthreads();
-    for (int a0 = wv; a0 < S; a0 += 8) {
-        const int a1 = a0 + 4;
-        double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
-        part_sums(p, d, a0, lane, c0, l0);
-        if (a1 < S) part_sums(p, d, a1, lane, c1, l1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c0[q] = wave_sum(c0[q]);
-            c1[q] = wave_sum(c1[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            l0[q] = wave_sum(l0[q]);
-            l1[q] = wave_sum(l1[q]);
-        }
-        if (lane == 0) {
-            decide_one(p, k, writer, d, a0, c0, l0);
-            if (a1 < S) decide_one(p, k, writer, d, a1, c1, l1);
-        }
-    }
-    __syncthreads();
-}
-
-// After k_entity: each thread first loads what it may select (both
-// candidates), then the restart decision is taken (every block, see decide),
-// then each partition's candidate is kept (eq. update_amm or update_mm), the
-// iterates roll and the next iteration's pair records and extrapolated
-// cameras are written.
-__global__ __launch_bounds__(256) void k_decide_select(Params p, int k) {
-    __shared__ DecideLds d;
-    const bool writer = blockIdx.x == 0;
+// End of a call, after iteration k - 1: its restart test (every block takes
+// it, block 0 stores it) and the chosen candidates written into both
+// candidate slots and the camera generation k % 3, so that x^k is stored
+// plainly whichever slot is read.
+__global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
+    __shared__ int s_rs[kMaxPart];
+    __shared__ double s_Fsh[kMaxPart];
+    restart_test_block(p, k - 1, blockIdx.x == 0, s_rs, s_Fsh);
+    uint64_t restart = 0;
+    for (int a = 0; a < p.S; ++a) restart |= (uint64_t)(s_rs[a] != 0) << a;
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.st[0].decided = 1;
+    const int par = (k + 1) & 1;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool is_cam = i < p.M;
-    const bool is_lm = !is_cam && i - p.M < p.N;
-    const int ci = (int)i;
-    const int li = (int)(i - p.M);
-    // landmark: the pair record and both candidates
-    double2 q0 = {}, q1 = {}, cm0 = {}, cm1 = {}, ca0 = {}, ca1 = {};
-    if (is_lm) {
-        const double2* pr = reinterpret_cast<const double2*>(p.lpair[k & 1] + (size_t)li * kLmPair);
-        q0 = pr[0];
-        q1 = pr[1];
-        const double2* m = reinterpret_cast<const double2*>(p.lcand[0] + (size_t)li * 4);
-        const double2* c = reinterpret_cast<const double2*>(p.lcand[1] + (size_t)li * 4);
-        cm0 = m[0];
-        cm1 = m[1];
-        ca0 = c[0];
-        ca1 = c[1];
-    }
-    decide(p, k, writer, d);
-    const DevState& sc = p.st[k & 1];
-    if (writer && threadIdx.x == 0) {
-        double s1;
-        const double gam = next_gamma(p, sc.s, &s1);
-        double F = 0.0;
-        for (int a = 0; a < p.S; ++a) F += d.Fsh[a];
-        if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
-        const int64_t kk = sc.k;
-        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
-        DevState& sn = p.st[(k + 1) & 1];
-        sn.F = F;
-        sn.s = s1;
-        sn.gamma = gam;
-        sn.k = kk + 1;
-    }
-    if (is_cam) {
-        const int rs = p.accelerate ? d.rs[p.cam_part[ci]] : 1;
-        // the chosen candidate and its extrapolation (computed in k_entity)
-        const double2* src = reinterpret_cast<const double2*>(p.cam_cand[rs ? 0 : 1] + (size_t)ci * kCamRec);
-        double2* dst = reinterpret_cast<double2*>(p.cams[(k + 1) % 3] + (size_t)ci * kCamRec);
+    if (i < p.M) {
+        const int ci = (int)i;
+        const int c = chosen(restart, p.cam_part[ci]);
+        const size_t o = (size_t)ci * kCamRec;
+        double2 x[8], xb[8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) dst[a] = src[a];
-        if (p.accelerate) {
-            const double2* sb = reinterpret_cast<const double2*>(p.cam_bar_cand[rs ? 0 : 1] + (size_t)ci * kCamRec);
-            double2* db = reinterpret_cast<double2*>(p.cam_bar + (size_t)ci * kCamRec);
+        for (int a = 0; a < 8; ++a) {
+            x[a] = reinterpret_cast<const double2*>(p.ccand[par][c] + o)[a];
+            xb[a] = reinterpret_cast<const double2*>(p.cbar[par][c] + o)[a];
+        }
 #pragma unroll
-            for (int a = 0; a < 8; ++a) db[a] = sb[a];
+        for (int a = 0; a < 8; ++a) {
+            reinterpret_cast<double2*>(p.ccand[par][0] + o)[a] = x[a];
+            reinterpret_cast<double2*>(p.ccand[par][1] + o)[a] = x[a];
+            reinterpret_cast<double2*>(p.cbar[par][0] + o)[a] = xb[a];
+            reinterpret_cast<double2*>(p.cbar[par][1] + o)[a] = xb[a];
+            reinterpret_cast<double2*>(p.cams[k % 3] + o)[a] = x[a];
         }
         return;
     }
-    if (is_lm) {
-        const int beta = (int)__double_as_longlong(q1.y);
-        const int rs = p.accelerate ? d.rs[beta] : 1;
-        const double2 n0 = rs ? cm0 : ca0, n1 = rs ? cm1 : ca1;  // next l: (x, y), (z, -)
-        double2* q = reinterpret_cast<double2*>(p.lpair[(k + 1) & 1] + (size_t)li * kLmPair);
-        q[0] = n0;
-        q[1] = make_double2(n1.x, q1.y);
-        q[2] = q0;
-        q[3] = make_double2(q1.x, 0.0);
+    const int64_t j = i - p.M;
+    if (j < p.N) {
+        const int li = (int)j;
+        const int c = chosen(restart, p.lm_part[li]);
+        const size_t o = (size_t)li * kLmPair;
+        double2 q[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) q[a] = reinterpret_cast<const double2*>(p.lcp[par][c] + o)[a];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            reinterpret_cast<double2*>(p.lcp[par][0] + o)[a] = q[a];
+            reinterpret_cast<double2*>(p.lcp[par][1] + o)[a] = q[a];
+        }
         if (p.fp32) {
-            float4* f = reinterpret_cast<float4*>(p.lpair32[(k + 1) & 1] + (size_t)li * kLmPair);
-            f[0] = make_float4((float)n0.x, (float)n0.y, (float)n1.x, __int_as_float(beta));
-            f[1] = make_float4((float)q0.x, (float)q0.y, (float)q1.x, 0.0f);
+            float4 f[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) f[a] = reinterpret_cast<const float4*>(p.lcp32[par][c] + o)[a];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                reinterpret_cast<float4*>(p.lcp32[par][0] + o)[a] = f[a];
+                reinterpret_cast<float4*>(p.lcp32[par][1] + o)[a] = f[a];
+            }
         }
     }
 }
@@ -1534,8 +1581,12 @@ __global__ __launch_bounds__(256) void k_extrapolate_cams(Params p, int k) {
     double cb[16];
     extrapolate_cam(p.cams[k % 3] + (size_t)ci * kCamRec, p.cams[(k + 2) % 3] + (size_t)ci * kCamRec,
                     p.st[k & 1].gamma, cb);
+    const int par = (k + 1) & 1;
 #pragma unroll
-    for (int a = 0; a < 16; ++a) p.cam_bar[(size_t)ci * kCamRec + a] = cb[a];
+    for (int a = 0; a < 16; ++a) {
+        p.cbar[par][0][(size_t)ci * kCamRec + a] = cb[a];
+        p.cbar[par][1][(size_t)ci * kCamRec + a] = cb[a];
+    }
 }
 
 // ------------------------------------------------------- objective shares
@@ -1569,7 +1620,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_objective(Params p, const 
         if (o < end) {
             const double2 u2 = uv[o];
             const R ux = (R)u2.x, uy = (R)u2.y;
-            const LmRead<double> L = read_pair(lpair, p.obs_lm[o]);
+            const LmRead<double> L = read_pair(lpair, p.obs_lm[o] & kLmMask);
             const R r2u = ux * ux + uy * uy;
             ObsEvalCF<LOSS, R> e;
             eval_obs_cf<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
@@ -1647,8 +1698,7 @@ __global__ __launch_bounds__(256) void k_import(Params p, const double* __restri
     }
     if (i < p.N) {
         double* dst = p.tmp_lpair + (size_t)i * kLmPair;
-        const double* cur = p.lpair[0];  // partition ids are the same in both buffers
-        const double beta = cur[(size_t)i * kLmPair + 3];
+        const double beta = __longlong_as_double((long long)p.lm_part[i]);
         if (lms) {
             const double* src = lms + (size_t)p.lm_ext[i] * 3;
             dst[0] = src[0];
@@ -1695,7 +1745,7 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_grad_obs(Params p, const d
         if (o < end) {
             const double2 u2 = uv[o];
             const R ux = (R)u2.x, uy = (R)u2.y;
-            const LmRead<double> L = read_pair(lpair, p.obs_lm[o]);
+            const LmRead<double> L = read_pair(lpair, p.obs_lm[o] & kLmMask);
             const R r2u = ux * ux + uy * uy;
             ObsEvalCF<LOSS, R> e;
             eval_obs_cf<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
@@ -1799,14 +1849,15 @@ __global__ __launch_bounds__(256) void k_grad_entities(Params p, double* __restr
 
 hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s) {
     if (p.T == 0) return hipSuccess;
-    dim3 grid((p.T + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
+    const int T1 = p.T;
+    dim3 grid((T1 + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
     DABA_LOSS_SWITCH(p.loss, {
         if (p.fp32) {
             if (p.accelerate) hipLaunchKernelGGL((k_obs<float, LS, true>), grid, block, 0, s, p, k);
             else hipLaunchKernelGGL((k_obs<float, LS, false>), grid, block, 0, s, p, k);
         } else {
-            if (p.accelerate) hipLaunchKernelGGL((k_obs64<LS, true>), dim3(p.T), dim3(kWave), 0, s, p, k);
-            else hipLaunchKernelGGL((k_obs64<LS, false>), dim3(p.T), dim3(kWave), 0, s, p, k);
+            if (p.accelerate) hipLaunchKernelGGL((k_obs64<LS, true>), dim3(T1), dim3(kWave), 0, s, p, k);
+            else hipLaunchKernelGGL((k_obs64<LS, false>), dim3(T1), dim3(kWave), 0, s, p, k);
         }
     });
     return hipGetLastError();
@@ -1824,9 +1875,14 @@ hipError_t launch_entity(const Params& p, int k, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_decide_select(const Params& p, int k, hipStream_t s) {
+hipError_t launch_decide(const Params& p, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, p, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Params& p, int k, hipStream_t s) {
     const int64_t n = p.M + p.N;
-    hipLaunchKernelGGL(k_decide_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, k);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, k);
     return hipGetLastError();
 }
 

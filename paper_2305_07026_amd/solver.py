@@ -105,8 +105,8 @@ class DabaSolver:
         return None
 
     def iterate_timed(self, n: int):
-        """n iterations; returns summed GPU ms of (observation pass, entity
-        solves, restart test with the selection)."""
+        """n iterations; returns summed GPU ms of (observation passes, entity
+        solves, the closing restart test of the call)."""
         ms = np.zeros(3)
         self._chk(B.lib.daba_iterate_timed(self._h, n, _ptr(ms, C.c_double)), "daba_iterate_timed")
         return ms
