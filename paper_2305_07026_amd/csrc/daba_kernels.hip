@@ -143,39 +143,43 @@ __device__ __forceinline__ void eval_obs_cf(const CamT<R>& c, R l0, R l1, R l2, 
 }
 
 // Moments of one surrogate (see header comment): a[0..19] = Z, a[20..37] = Y.
+// The per-observation quantities (FP32 in the mixed form) are widened once;
+// products and sums are FP64.
 template <typename R>
-__device__ __forceinline__ void add_moments(double* a, R w, R lam, R ux, R uy, R r2, R r4, R r6, R r8,
+__device__ __forceinline__ void add_moments(double* a, R w_, R lam_, R ux_, R uy_, R r2_, R r4_, R r6_, R r8_,
                                             const R* e) {
-    R wu = w * ux, wv = w * uy, wl = w * lam;
-    a[0] += (double)(wu * ux);
-    a[1] += (double)(wu * uy);
-    a[2] += (double)(wv * uy);
-    a[3] += (double)wu;
-    a[4] += (double)(wu * r2);
-    a[5] += (double)(wu * r4);
-    a[6] += (double)wv;
-    a[7] += (double)(wv * r2);
-    a[8] += (double)(wv * r4);
-    a[9] += (double)w;
-    a[10] += (double)(w * r2);
-    a[11] += (double)(w * r4);
-    a[12] += (double)(w * r6);
-    a[13] += (double)(w * r8);
-    a[14] += (double)(wl * ux);
-    a[15] += (double)(wl * uy);
-    a[16] += (double)wl;
-    a[17] += (double)(wl * r2);
-    a[18] += (double)(wl * r4);
-    a[19] += (double)(wl * lam);
+    const double w = (double)w_, lam = (double)lam_, ux = (double)ux_, uy = (double)uy_;
+    const double r2 = (double)r2_, r4 = (double)r4_, r6 = (double)r6_, r8 = (double)r8_;
+    const double wu = w * ux, wv = w * uy, wl = w * lam;
+    a[0] += wu * ux;
+    a[1] += wu * uy;
+    a[2] += wv * uy;
+    a[3] += wu;
+    a[4] += wu * r2;
+    a[5] += wu * r4;
+    a[6] += wv;
+    a[7] += wv * r2;
+    a[8] += wv * r4;
+    a[9] += w;
+    a[10] += w * r2;
+    a[11] += w * r4;
+    a[12] += w * r6;
+    a[13] += w * r8;
+    a[14] += wl * ux;
+    a[15] += wl * uy;
+    a[16] += wl;
+    a[17] += wl * r2;
+    a[18] += wl * r4;
+    a[19] += wl * lam;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        R g = (R)0.5 * w * e[k];  // w r^y with r^y = e_w / 2
-        a[20 + 6 * k + 0] += (double)(g * ux);
-        a[20 + 6 * k + 1] += (double)(g * uy);
-        a[20 + 6 * k + 2] += (double)g;
-        a[20 + 6 * k + 3] += (double)(g * r2);
-        a[20 + 6 * k + 4] += (double)(g * r4);
-        a[20 + 6 * k + 5] += (double)(g * lam);
+        const double g = 0.5 * w * (double)e[k];  // w r^y with r^y = e_w / 2
+        a[20 + 6 * k + 0] += g * ux;
+        a[20 + 6 * k + 1] += g * uy;
+        a[20 + 6 * k + 2] += g;
+        a[20 + 6 * k + 3] += g * r2;
+        a[20 + 6 * k + 4] += g * r4;
+        a[20 + 6 * k + 5] += g * lam;
     }
 }
 
@@ -203,32 +207,6 @@ __device__ __forceinline__ LmRead<float> read_pair(const float* __restrict__ bas
     o.beta = __float_as_int(a.w);
     o.lp[0] = b.x; o.lp[1] = b.y; o.lp[2] = b.z;
     return o;
-}
-
-__device__ __forceinline__ void write_rec(double* __restrict__ rec, int slot, const double* v) {
-    double4* q = reinterpret_cast<double4*>(rec + (size_t)slot * 8);
-    q[0] = make_double4(v[0], v[1], v[2], v[3]);
-    q[1] = make_double4(v[4], v[5], v[6], v[7]);
-}
-__device__ __forceinline__ void write_rec(float* __restrict__ rec, int slot, const float* v) {
-    float4* q = reinterpret_cast<float4*>(rec + (size_t)slot * 8);
-    q[0] = make_float4(v[0], v[1], v[2], v[3]);
-    q[1] = make_float4(v[4], v[5], v[6], v[7]);
-}
-
-template <typename R>
-__device__ __forceinline__ void load_uv(const Params& p, int o, R& ux, R& uy);
-template <>
-__device__ __forceinline__ void load_uv<double>(const Params& p, int o, double& ux, double& uy) {
-    double2 u = p.uv[o];
-    ux = u.x;
-    uy = u.y;
-}
-template <>
-__device__ __forceinline__ void load_uv<float>(const Params& p, int o, float& ux, float& uy) {
-    float2 u = p.uv32[o];
-    ux = u.x;
-    uy = u.y;
 }
 
 // candidate pair records read by iteration k (written by iteration k - 1)
@@ -404,195 +382,41 @@ __device__ __forceinline__ uint64_t restart_mask(const Params& p) {
 // candidate chosen for partition a: 0 (plain MM) on restart, else 1
 __device__ __forceinline__ int chosen(uint64_t restart, int a) { return ((restart >> a) & 1) ? 0 : 1; }
 
-// ------------------------------------------------------- observation pass
-
-constexpr int kAcc = 78;   // 2 x 38 moments + F share + gap share
-constexpr int kRedCh = 20; // values per LDS transpose round
-
-template <typename R, int LOSS, bool ACC>
-__global__ __launch_bounds__(kObsWaves* kWave) void k_obs(Params p, int k) {
-    __shared__ double red[kObsWaves][kRedCh * (kWave + 1)];
-    __shared__ double bins[kObsWaves][2][kMaxPart];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int t = uniform_int(blockIdx.x * kObsWaves + wv);
-    const bool active = t < p.T;
-    const int S = p.S;
-
-    for (int b = lane; b < S; b += kWave) {
-        bins[wv][0][b] = 0.0;
-        bins[wv][1][b] = 0.0;
-    }
-
-    double acc[kAcc];
-#pragma unroll
-    for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
-
-    const uint64_t rmask = restart_mask(p);
-    int beg = 0, end = 0, ci = 0, alpha = 0;
-    if (active) {
-        ci = uniform_int(p.tile_cam[t]);
-        beg = uniform_int(p.tile_begin[t]);
-        end = uniform_int(p.tile_end[t]);
-        alpha = uniform_int(p.cam_part[ci]);
-    }
-    const int cc = chosen(rmask, alpha);
-    const CamT<R> ck = load_cam<R>(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
-    const CamT<R> cp = load_cam<R>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
-    CamT<R> cb;
-    if constexpr (ACC) cb = load_cam<R>(p.cbar[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
-    const R gam = ACC ? (R)p.st[k & 1].gamma : (R)0;
-    const R delta = (R)p.delta;
-    const R* __restrict__ pairs0 = pair_base<R>(p, k, 0);
-    const R* __restrict__ pairs1 = pair_base<R>(p, k, 1);
-    R* __restrict__ rec = rec_base<R>(p);
-    bool bad = false;
-    int run_key = -1;       // wave-uniform landmark partition of the open run
-    double run0 = 0.0, run1 = 0.0;
-    __syncthreads();
-
-    int li_next = beg + lane < end ? p.obs_lm[beg + lane] : 0;  // with the partition in the top bits
-    for (int base = beg; base < end; base += kWave) {
-        const int o = base + lane;
-        const bool on = o < end;
-        // the next step's landmark index is requested before this step's
-        // gather, so each step waits for one memory round trip, not two
-        const int li = li_next;
-        li_next = o + kWave < end ? p.obs_lm[o + kWave] : 0;
-        double hF = 0.0, gp = 0.0;
-        int key = -1;
-        if (on) {
-            R ux, uy;
-            load_uv<R>(p, o, ux, uy);
-            const int slot = p.obs_slot[o];
-            const LmRead<R> L = read_pair(chosen(rmask, li >> kLmBits) ? pairs1 : pairs0, li & kLmMask);
-            const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
-            const R r6u = r4u * r2u, r8u = r4u * r4u;
-
-            ObsEval<LOSS, R> ek;
-            eval_obs<LOSS, R>(ck, L.lk[0], L.lk[1], L.lk[2], ux, uy, r2u, r4u, delta, ek);
-            bad |= !(ek.r2 > (R)1e-24);
-            add_moments<R>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
-            // landmark-side record: W = w lambda^2 and V = w lambda e_w per surrogate
-            R rv[8];
-            rv[0] = ek.w * ek.lam * ek.lam;
-            rv[1] = ek.w * ek.lam * ek.e[0];
-            rv[2] = ek.w * ek.lam * ek.e[1];
-            rv[3] = ek.w * ek.lam * ek.e[2];
-            rv[4] = rv[5] = rv[6] = rv[7] = (R)0;
-            if constexpr (ACC) {
-                R lb0 = L.lk[0] + gam * (L.lk[0] - L.lp[0]);
-                R lb1 = L.lk[1] + gam * (L.lk[1] - L.lp[1]);
-                R lb2 = L.lk[2] + gam * (L.lk[2] - L.lp[2]);
-                ObsEval<LOSS, R> eb;
-                eval_obs<LOSS, R>(cb, lb0, lb1, lb2, ux, uy, r2u, r4u, delta, eb);
-                bad |= !(eb.r2 > (R)1e-24);
-                add_moments<R>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
-                rv[4] = eb.w * eb.lam * eb.lam;
-                rv[5] = eb.w * eb.lam * eb.e[0];
-                rv[6] = eb.w * eb.lam * eb.e[1];
-                rv[7] = eb.w * eb.lam * eb.e[2];
-            }
-            write_rec(rec, slot, rv);
-            // F share: each side of the pair gets half of F_ij = rho / 2
-            hF = (double)((R)0.25 * ek.rho);
-            key = L.beta;
-            if (L.beta != alpha) {
-                // surrogate gap of the previous linearization y = x^(k-1) at x^k:
-                // P - Q = w (|Dc|^2 - |Dl|^2 + e^y . (Dc + Dl)) with
-                // Dc = R^k p^k - R^y p^y + lambda^y (t^k - t^y), Dl = lambda^y (l^k - l^y)
-                ObsEval<LOSS, R> ep;
-                eval_obs<LOSS, R>(cp, L.lp[0], L.lp[1], L.lp[2], ux, uy, r2u, r4u, delta, ep);
-                R dc[3], dl[3], q = (R)0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    dc[a] = ek.Rp[a] - ep.Rp[a] + ep.lam * (ck.t[a] - cp.t[a]);
-                    dl[a] = ep.lam * (L.lk[a] - L.lp[a]);
-                    q += dc[a] * dc[a] - dl[a] * dl[a] + ep.e[a] * (dc[a] + dl[a]);
-                }
-                gp = (double)((R)0.5 * ep.w * q);
-            }
-        }
-        acc[2 * kMom] += hF;
-        acc[2 * kMom + 1] += gp;
-        if (S > 1) {
-            // landmark-side shares by landmark partition.  Within a camera the
-            // observations are sorted by landmark partition, so most steps
-            // hold one partition: accumulate those per lane and reduce once
-            // per run; a step that straddles partitions uses a segmented sum.
-            const int k0 = uniform_int(key);
-            const bool uni = __all(!on || key == k0);
-            if (uni) {
-                if (k0 != run_key) {
-                    flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
-                    run_key = k0;
-                }
-                run0 += hF;
-                run1 -= gp;
-            } else {
-                flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
-                run_key = -1;
-                bin_add_sorted(hF, -gp, key, lane, bins[wv][0], bins[wv][1]);
-            }
-        }
-    }
-    if (S > 1) flush_run(run_key, run0, run1, lane, bins[wv][0], bins[wv][1]);
-    if (bad) p.st[0].err = -5;
-
-    // tile totals: LDS transpose, lane v sums value v over the 64 lanes
-    double* rw = red[wv];
-#pragma unroll
-    for (int c0 = 0; c0 < kAcc; c0 += kRedCh) {
-#pragma unroll
-        for (int v = 0; v < kRedCh; ++v)
-            if (c0 + v < kAcc) rw[v * (kWave + 1) + lane] = acc[c0 + v];
-        __syncthreads();
-        if (active && lane < kRedCh && c0 + lane < kAcc) {
-            double s = 0.0;
-            const double* row = rw + lane * (kWave + 1);
-            for (int q = 0; q < kWave; ++q) s += row[q];
-            p.tile_vals[(size_t)t * kTileVals + c0 + lane] = s;
-        }
-        __syncthreads();
-    }
-    if (active) {
-        if (S == 1) {
-            // one partition: the landmark side of every pair belongs to it
-            if (lane == 0) {
-                p.tile_bins[t] = p.tile_vals[(size_t)t * kTileVals + 2 * kMom];
-                p.tile_bins[(size_t)p.T + t] = -p.tile_vals[(size_t)t * kTileVals + 2 * kMom + 1];
-            }
-        } else {
-            for (int b = lane; b < S; b += kWave) {
-                p.tile_bins[(size_t)b * p.T + t] = bins[wv][0][b];
-                p.tile_bins[(size_t)(S + b) * p.T + t] = bins[wv][1][b];
-            }
-        }
-    }
-}
-
-// ------------------------------------------- observation pass, FP64 form
-// The same pass with its memory traffic restructured for gfx950:
+// ------------------------------------- observation pass, restructured form
+// The observation pass with its memory traffic restructured for gfx950
+// (FP64, and FP32-mixed with 32-byte records):
 //  * a step's 64 landmark pair records are fetched straight into LDS
-//    (global_load_lds, no VGPRs), four lanes per 64-byte record so that each
-//    wave instruction touches 16 cache lines instead of 64; pixels and slots
-//    come the same way.  The fetch for step s + 1 is issued while step s
-//    computes, into the other of two buffers, and the landmark indices it
-//    needs are loaded one step earlier still;
+//    (global_load_lds, no VGPRs), several lanes per record (16 bytes each) so
+//    that a wave instruction touches a few cache lines instead of 64; pixels
+//    and slots come the same way.  The fetch for step s + 1 is issued while
+//    step s computes, into the other of two buffers, and the landmark
+//    indices it needs are loaded one step earlier still;
 //  * the landmark-side records of step s are staged in LDS and written at
-//    the start of step s + 1, again four lanes per record.  On this target
-//    a load's wait also waits for every store issued before it, so stores go
-//    out right after a step's wait, a whole step ahead of the next one.
+//    the start of step s + 1, again several lanes per record.  On this
+//    target a load's wait also waits for every store issued before it, so
+//    stores go out right after a step's wait, a whole step ahead of the next.
 // Every wave waits for all of its vector memory operations at the start of
 // a step, explicitly: the compiler does not order an LDS read after an LDS
 // DMA into the same object.  The two buffers are separate objects, so that
 // reading one while the other is being filled needs no wait.
-struct ObsBuf {
+constexpr int kRedHalf = 7;  // rows of the reduction transpose per buffer (7 x 65 <= 512)
+template <typename R>
+struct ObsBuf;
+template <>
+struct __align__(16) ObsBuf<double> {
     double pair[kWave * kLmPair];  // pair records of a step, in observation order
     double2 uv[kWave];
     int slot[kWave];
+    __device__ double* red() { return pair; }  // reused for the tile reduction
 };
-constexpr int kRedHalf = 7;  // rows of the reduction transpose per buffer (7 x 65 <= 512)
+template <>
+struct __align__(16) ObsBuf<float> {
+    float pair[kWave * kLmPair];
+    float ux[kWave], uy[kWave];
+    int slot[kWave];
+    double red_[kRedHalf * (kWave + 1)];
+    __device__ double* red() { return red_; }
+};
 static_assert(kRedHalf * (kWave + 1) <= kWave * kLmPair, "reduction fits a pair buffer");
 
 typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -614,12 +438,19 @@ __device__ __forceinline__ void wait_vmem() {
 // One wave per workgroup (one tile each): every LDS address is then a
 // compile-time offset from the lane's own, which keeps VGPRs for the 78
 // FP64 accumulators.
-template <int LOSS, bool ACC>
-__global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
-    __shared__ ObsBuf A;
-    __shared__ ObsBuf B;
-    __shared__ double stg[kWave * 8];  // landmark-side records of a step
+template <typename R, int LOSS, bool ACC>
+__global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
+    constexpr int kRecB = 8 * (int)sizeof(R);  // bytes of a pair record and of a landmark-side record
+    constexpr int kLPR = kRecB / 16;           // lanes per record
+    constexpr int kRPI = kWave / kLPR;         // records per wave instruction
+    constexpr int kNI = kWave / kRPI;          // instructions per step
+    constexpr int kEPC = 16 / (int)sizeof(R);  // elements per 16-byte chunk
+    __shared__ ObsBuf<R> A;
+    __shared__ ObsBuf<R> B;
+    __shared__ __align__(16) R stg[kWave * 8];  // landmark-side records of a step
     __shared__ double bins[2][kMaxPart];
+    __shared__ double cprev[kCamRec];  // x^(k-1) of the tile's camera (used by the gap only)
+    __shared__ double cbarl[kCamRec];  // x-bar^k of the tile's camera
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
     const bool active = t < p.T;
@@ -630,9 +461,12 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         bins[1][b] = 0.0;
     }
 
-    double acc[kAcc];
+    // the 2 x 38 moments; the tile's F and gap shares are the sums of its
+    // partition bins
+    constexpr int kAccR = 2 * kMom;
+    double acc[kAccR];
 #pragma unroll
-    for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
+    for (int a = 0; a < kAccR; ++a) acc[a] = 0.0;
 
     const uint64_t restart = restart_mask(p);
     int beg = 0, end = 0, ci = 0, alpha = 0;
@@ -643,17 +477,16 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         alpha = uniform_int(p.cam_part[ci]);
     }
     const int cc = chosen(restart, alpha);
-    const CamT<double> ck = load_cam<double>(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
-    const CamT<double> cp = load_cam<double>(p.cams[(k + 2) % 3] + (size_t)ci * kCamRec);
-    CamT<double> cb;
-    if constexpr (ACC) cb = load_cam<double>(p.cbar[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
-    const double gam = ACC ? p.st[k & 1].gamma : 0.0;
-    const double delta = p.delta;
+    const CamT<R> ck = load_cam<R>(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
+    if (lane < kCamRec) cprev[lane] = p.cams[(k + 2) % 3][(size_t)ci * kCamRec + lane];
+    if (ACC && lane < kCamRec) cbarl[lane] = p.cbar[(k + 1) & 1][cc][(size_t)ci * kCamRec + lane];
+    const R gam = ACC ? (R)p.st[k & 1].gamma : (R)0;
+    const R delta = (R)p.delta;
     // both candidate buffers of a parity are one allocation: candidate 1
     // follows candidate 0 after N records
-    const char* __restrict__ pbase = reinterpret_cast<const char*>(p.lcp[(k + 1) & 1][0]);
-    const uint64_t cand_stride = (uint64_t)p.N * (kLmPair * 8);
-    double* __restrict__ rec = p.rec;
+    const char* __restrict__ pbase = reinterpret_cast<const char*>(pair_base<R>(p, k, 0));
+    const uint64_t cand_stride = (uint64_t)p.N * kRecB;
+    R* __restrict__ rec = rec_base<R>(p);
     bool bad = false;
     int run_key = -1;
     double run0 = 0.0, run1 = 0.0;
@@ -661,8 +494,9 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
 
     const int last = end - 1;  // tiles are never empty
     const int ns = active ? (end - beg + kWave - 1) / kWave : 0;
-    // landmark index of each lane's observation, one step ahead of the fetch;
-    // lane 4r + c fetches chunk c of record 16 i + r in instruction i
+    // landmark index (with its partition in the top bits) of each lane's
+    // observation, one step ahead of the fetch; lane kLPR r + c fetches
+    // chunk c of record kRPI i + r in instruction i
     int li_ahead = 0;
     auto load_li = [&](int st) { li_ahead = p.obs_lm[min(beg + kWave * st + lane, last)]; };
     // Lane-derived offsets are recomputed inside each step from a lane index
@@ -673,35 +507,40 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         asm volatile("" : "+v"(l));
         return l;
     };
-    auto fetch = [&](int st, ObsBuf& D) {
-        const int ln = opaque_lane(), quad = ln >> 2, qc = ln & 3;
+    auto fetch = [&](int st, ObsBuf<R>& D) {
+        const int ln = opaque_lane(), rr = ln / kLPR, qc = ln % kLPR;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const unsigned lp = (unsigned)__shfl(li_ahead, 16 * i + quad);
+        for (int i = 0; i < kNI; ++i) {
+            const unsigned lp = (unsigned)__shfl(li_ahead, kRPI * i + rr);
             const unsigned li = lp & kLmMask;
             const uint64_t off = (uint64_t)chosen(restart, (int)(lp >> kLmBits)) * cand_stride +
-                                 (uint64_t)li * (kLmPair * 8) + 16u * qc;
-            dma16(pbase + off, &D.pair[16 * i * kLmPair]);
+                                 (uint64_t)li * kRecB + 16u * qc;
+            dma16(pbase + off, &D.pair[kRPI * i * 8]);
         }
         const unsigned o = (unsigned)min(beg + kWave * st + ln, last);
-        dma16(reinterpret_cast<const char*>(p.uv) + 16u * o, &D.uv[0]);
+        if constexpr (sizeof(R) == 8) {
+            dma16(reinterpret_cast<const char*>(p.uv) + 16u * o, &D.uv[0]);
+        } else {
+            dma4(reinterpret_cast<const char*>(p.uv32) + 8u * o, &D.ux[0]);
+            dma4(reinterpret_cast<const char*>(p.uv32) + 8u * o + 4u, &D.uy[0]);
+        }
         dma4(reinterpret_cast<const char*>(p.obs_slot) + 4u * o, &D.slot[0]);
     };
     // records of step st (staged) to their slots (in D, the buffer of step st)
-    auto store_recs = [&](int st, const ObsBuf& D) {
-        const int ln = opaque_lane(), quad = ln >> 2, qc = ln & 3;
+    auto store_recs = [&](int st, const ObsBuf<R>& D) {
+        const int ln = opaque_lane(), rr = ln / kLPR, qc = ln % kLPR;
         const int b0 = beg + kWave * st;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * i + quad;
+        for (int i = 0; i < kNI; ++i) {
+            const int r = kRPI * i + rr;
             if (b0 + r < end) {
-                const double2 v = *reinterpret_cast<const double2*>(&stg[r * 8 + 2 * qc]);
-                *reinterpret_cast<double2*>(rec + (size_t)D.slot[r] * 8 + 2 * qc) = v;
+                const float4 v = *reinterpret_cast<const float4*>(&stg[r * 8 + kEPC * qc]);
+                *reinterpret_cast<float4*>(rec + (size_t)D.slot[r] * 8 + kEPC * qc) = v;
             }
         }
     };
     // step st reads buffer C; the next step's data goes to N
-    auto step = [&](int st, const ObsBuf& C, ObsBuf& N) {
+    auto step = [&](int st, const ObsBuf<R>& C, ObsBuf<R>& N) {
         wait_vmem();
         if (st > 0) store_recs(st - 1, N);
         __builtin_amdgcn_sched_barrier(0);
@@ -716,72 +555,97 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         double hF = 0.0, gp = 0.0;
         int key = -1;
         if (on) {
-            const double2 u2 = C.uv[ln];
-            const double* pr = &C.pair[ln * kLmPair];
-            const double2 q0 = *reinterpret_cast<const double2*>(pr);
-            const double2 q1 = *reinterpret_cast<const double2*>(pr + 2);
-            const double lk0 = q0.x, lk1 = q0.y, lk2 = q1.x;
-            const int beta = (int)__double_as_longlong(q1.y);
-            const double ux = u2.x, uy = u2.y;
-            const double r2u = ux * ux + uy * uy, r4u = r2u * r2u;
-            const double r6u = r4u * r2u, r8u = r4u * r4u;
-            double2* sg = reinterpret_cast<double2*>(&stg[ln * 8]);
-            ObsEval<LOSS, double> ek;
-            eval_obs<LOSS, double>(ck, lk0, lk1, lk2, ux, uy, r2u, r4u, delta, ek);
-            bad |= !(ek.r2 > 1e-24);
-            add_moments<double>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
-            // landmark-side record: W = w lambda^2 and V = w lambda e_w per surrogate
-            const double wl = ek.w * ek.lam;
-            sg[0] = make_double2(wl * ek.lam, wl * ek.e[0]);
-            sg[1] = make_double2(wl * ek.e[1], wl * ek.e[2]);
-            if constexpr (ACC) {
+            R ux, uy, lk0, lk1, lk2, lp0, lp1, lp2;
+            int beta;
+            const R* pr = &C.pair[ln * 8];
+            if constexpr (sizeof(R) == 8) {
+                const double2 u2 = C.uv[ln];
+                ux = u2.x;
+                uy = u2.y;
+                const double2 q0 = *reinterpret_cast<const double2*>(pr);
+                const double2 q1 = *reinterpret_cast<const double2*>(pr + 2);
                 const double2 q2 = *reinterpret_cast<const double2*>(pr + 4);
-                const double lp2 = pr[6];
-                const double lb0 = lk0 + gam * (lk0 - q2.x);
-                const double lb1 = lk1 + gam * (lk1 - q2.y);
-                const double lb2 = lk2 + gam * (lk2 - lp2);
-                ObsEval<LOSS, double> eb;
-                eval_obs<LOSS, double>(cb, lb0, lb1, lb2, ux, uy, r2u, r4u, delta, eb);
-                bad |= !(eb.r2 > 1e-24);
-                add_moments<double>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
-                const double wb = eb.w * eb.lam;
-                sg[2] = make_double2(wb * eb.lam, wb * eb.e[0]);
-                sg[3] = make_double2(wb * eb.e[1], wb * eb.e[2]);
+                lk0 = q0.x; lk1 = q0.y; lk2 = q1.x;
+                beta = (int)__double_as_longlong(q1.y);
+                lp0 = q2.x; lp1 = q2.y; lp2 = pr[6];
             } else {
-                sg[2] = make_double2(0.0, 0.0);
-                sg[3] = make_double2(0.0, 0.0);
+                ux = C.ux[ln];
+                uy = C.uy[ln];
+                const float4 f0 = *reinterpret_cast<const float4*>(pr);
+                const float4 f1 = *reinterpret_cast<const float4*>(pr + 4);
+                lk0 = f0.x; lk1 = f0.y; lk2 = f0.z;
+                beta = __float_as_int(f0.w);
+                lp0 = f1.x; lp1 = f1.y; lp2 = f1.z;
             }
+            const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
+            const R r6u = r4u * r2u, r8u = r4u * r4u;
+            R* sg = &stg[ln * 8];
+            ObsEval<LOSS, R> ek;
+            eval_obs<LOSS, R>(ck, lk0, lk1, lk2, ux, uy, r2u, r4u, delta, ek);
+            bad |= !(ek.r2 > (R)1e-24);
+            add_moments<R>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
+            // landmark-side record: W = w lambda^2 and V = w lambda e_w per surrogate
+            const R wl = ek.w * ek.lam;
+            sg[0] = wl * ek.lam;
+            sg[1] = wl * ek.e[0];
+            sg[2] = wl * ek.e[1];
+            sg[3] = wl * ek.e[2];
             // F share: each side of the pair gets half of F_ij = rho / 2
-            hF = 0.25 * ek.rho;
+            hF = (double)((R)0.25 * ek.rho);
             key = beta;
             if (beta != alpha) {
                 // surrogate gap of the previous linearization y = x^(k-1) at x^k:
                 // P - Q = w (|Dc|^2 - |Dl|^2 + e^y . (Dc + Dl)) with
                 // Dc = R^k p^k - R^y p^y + lambda^y (t^k - t^y), Dl = lambda^y (l^k - l^y)
-                const double2 q2 = *reinterpret_cast<const double2*>(pr + 4);
-                const double lp[3] = {q2.x, q2.y, pr[6]};
-                const double lk[3] = {lk0, lk1, lk2};
-                ObsEval<LOSS, double> ep;
-                eval_obs<LOSS, double>(cp, lp[0], lp[1], lp[2], ux, uy, r2u, r4u, delta, ep);
+                const R lp[3] = {lp0, lp1, lp2};
+                const R lk[3] = {lk0, lk1, lk2};
+                // x^(k-1) from LDS, through an address the optimizer cannot
+                // hoist: kept in SGPRs with the other two cameras it would
+                // spill them
+                int co = 0;
+                asm volatile("" : "+v"(co));
+                const CamT<R> cp = load_cam<R>(cprev + co);
+                ObsEval<LOSS, R> ep;
+                eval_obs<LOSS, R>(cp, lp0, lp1, lp2, ux, uy, r2u, r4u, delta, ep);
                 // R^k p^k again (cheaper than keeping it live), and the camera
                 // terms as separate products so that no difference of two
                 // loop-invariant values is kept in registers
-                const double pz = ck.d[0] + ck.d[1] * r2u + ck.d[2] * r4u;
-                double q = 0.0;
+                const R pz = ck.d[0] + ck.d[1] * r2u + ck.d[2] * r4u;
+                R q = (R)0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double rpk = ck.r[3 * a] * ux + ck.r[3 * a + 1] * uy + ck.r[3 * a + 2] * pz;
-                    const double dc = rpk - ep.Rp[a] + ep.lam * ck.t[a] - ep.lam * cp.t[a];
-                    const double dl = ep.lam * (lk[a] - lp[a]);
+                    const R rpk = ck.r[3 * a] * ux + ck.r[3 * a + 1] * uy + ck.r[3 * a + 2] * pz;
+                    const R dc = rpk - ep.Rp[a] + ep.lam * ck.t[a] - ep.lam * cp.t[a];
+                    const R dl = ep.lam * (lk[a] - lp[a]);
                     q += dc * dc - dl * dl + ep.e[a] * (dc + dl);
                 }
-                gp = 0.5 * ep.w * q;
+                gp = (double)((R)0.5 * ep.w * q);
+            }
+            if constexpr (ACC) {
+                const R lb0 = lk0 + gam * (lk0 - lp0);
+                const R lb1 = lk1 + gam * (lk1 - lp1);
+                const R lb2 = lk2 + gam * (lk2 - lp2);
+                int co = 0;
+                asm volatile("" : "+v"(co));
+                const CamT<R> cb = load_cam<R>(cbarl + co);
+                ObsEval<LOSS, R> eb;
+                eval_obs<LOSS, R>(cb, lb0, lb1, lb2, ux, uy, r2u, r4u, delta, eb);
+                bad |= !(eb.r2 > (R)1e-24);
+                add_moments<R>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
+                const R wb = eb.w * eb.lam;
+                sg[4] = wb * eb.lam;
+                sg[5] = wb * eb.e[0];
+                sg[6] = wb * eb.e[1];
+                sg[7] = wb * eb.e[2];
+            } else {
+                sg[4] = sg[5] = sg[6] = sg[7] = (R)0;
             }
         }
-        acc[2 * kMom] += hF;
-        acc[2 * kMom + 1] += gp;
-        if (S > 1) {
-            // landmark-side shares by landmark partition (see k_obs)
+        {
+            // landmark-side shares by landmark partition.  Within a camera the
+            // observations are sorted by landmark partition, so most steps
+            // hold one partition: accumulate those per lane and reduce once
+            // per run; a step that straddles partitions uses a segmented sum.
             const int k0 = uniform_int(key);
             const bool uni = __all(!on || key == k0);
             if (uni) {
@@ -810,26 +674,28 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
     }
     wait_vmem();
     if (ns > 0) store_recs(ns - 1, (ns - 1) & 1 ? B : A);
-    if (S > 1) flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
+    flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
     if (bad) p.st[0].err = -5;
 
-    // tile totals: LDS transpose in the two pair buffers (rows 0..6 in A,
-    // 7..13 in B), lane v sums value v over the 64 lanes
+    // tile totals: LDS transpose in the two buffers (rows 0..6 in A, 7..13
+    // in B), lane v sums value v over the 64 lanes
     wait_vmem();
     constexpr int kCh = 2 * kRedHalf;
+    double* redA = A.red();
+    double* redB = B.red();
 #pragma unroll
-    for (int c0 = 0; c0 < kAcc; c0 += kCh) {
+    for (int c0 = 0; c0 < kAccR; c0 += kCh) {
 #pragma unroll
         for (int v = 0; v < kCh; ++v) {
-            if (c0 + v < kAcc) {
-                double* row = v < kRedHalf ? &A.pair[v * (kWave + 1)] : &B.pair[(v - kRedHalf) * (kWave + 1)];
+            if (c0 + v < kAccR) {
+                double* row = v < kRedHalf ? &redA[v * (kWave + 1)] : &redB[(v - kRedHalf) * (kWave + 1)];
                 row[lane] = acc[c0 + v];
             }
         }
         __syncthreads();
-        if (active && lane < kCh && c0 + lane < kAcc) {
-            const double* row = lane < kRedHalf ? &A.pair[lane * (kWave + 1)]
-                                                : &B.pair[(lane - kRedHalf) * (kWave + 1)];
+        if (active && lane < kCh && c0 + lane < kAccR) {
+            const double* row = lane < kRedHalf ? &redA[lane * (kWave + 1)]
+                                                : &redB[(lane - kRedHalf) * (kWave + 1)];
             double sum = 0.0;
             for (int q = 0; q < kWave; ++q) sum += row[q];
             p.tile_vals[(size_t)t * kTileVals + c0 + lane] = sum;
@@ -837,16 +703,18 @@ __global__ __launch_bounds__(kWave) void k_obs64(Params p, int k) {
         __syncthreads();
     }
     if (active) {
-        if (S == 1) {
-            if (lane == 0) {
-                p.tile_bins[t] = p.tile_vals[(size_t)t * kTileVals + 2 * kMom];
-                p.tile_bins[(size_t)p.T + t] = -p.tile_vals[(size_t)t * kTileVals + 2 * kMom + 1];
+        for (int b = lane; b < S; b += kWave) {
+            p.tile_bins[(size_t)b * p.T + t] = bins[0][b];
+            p.tile_bins[(size_t)(S + b) * p.T + t] = bins[1][b];
+        }
+        if (lane == 0) {
+            double f = 0.0, g = 0.0;
+            for (int b = 0; b < S; ++b) {
+                f += bins[0][b];
+                g += bins[1][b];
             }
-        } else {
-            for (int b = lane; b < S; b += kWave) {
-                p.tile_bins[(size_t)b * p.T + t] = bins[0][b];
-                p.tile_bins[(size_t)(S + b) * p.T + t] = bins[1][b];
-            }
+            p.tile_vals[(size_t)t * kTileVals + 2 * kMom] = f;
+            p.tile_vals[(size_t)t * kTileVals + 2 * kMom + 1] = -g;
         }
     }
 }
@@ -1853,11 +1721,11 @@ hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s) {
     dim3 grid((T1 + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
     DABA_LOSS_SWITCH(p.loss, {
         if (p.fp32) {
-            if (p.accelerate) hipLaunchKernelGGL((k_obs<float, LS, true>), grid, block, 0, s, p, k);
-            else hipLaunchKernelGGL((k_obs<float, LS, false>), grid, block, 0, s, p, k);
+            if (p.accelerate) hipLaunchKernelGGL((k_obs_dma<float, LS, true>), dim3(T1), dim3(kWave), 0, s, p, k);
+            else hipLaunchKernelGGL((k_obs_dma<float, LS, false>), dim3(T1), dim3(kWave), 0, s, p, k);
         } else {
-            if (p.accelerate) hipLaunchKernelGGL((k_obs64<LS, true>), dim3(T1), dim3(kWave), 0, s, p, k);
-            else hipLaunchKernelGGL((k_obs64<LS, false>), dim3(T1), dim3(kWave), 0, s, p, k);
+            if (p.accelerate) hipLaunchKernelGGL((k_obs_dma<double, LS, true>), dim3(T1), dim3(kWave), 0, s, p, k);
+            else hipLaunchKernelGGL((k_obs_dma<double, LS, false>), dim3(T1), dim3(kWave), 0, s, p, k);
         }
     });
     return hipGetLastError();
