@@ -609,6 +609,10 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         h->d_obj = objective_scratch(L, fp32, static_cast<char*>(dev_workspace));
         p.M = L.M; p.N = L.N; p.K = L.K; p.S = L.S; p.T = L.T; p.G = L.G;
         p.nCamBlocks = (int)L.camblock_c0.size();
+        for (int a = 0; a <= L.S; ++a) {
+            p.pcb[a] = L.part_camblk[a];
+            p.plb[a] = L.part_lmblk[a];
+        }
         p.nLmBlocks = (int)L.lmblock_g0.size();
         p.loss = opt->loss;
         p.scale = prob->unit_scale;

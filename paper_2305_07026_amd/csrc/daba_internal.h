@@ -87,6 +87,8 @@ struct Params {
     const int* camblock_c1;
     const int* part_camblk;   // [S+1] camera blocks of each partition
     const int* part_lmblk;    // [S+1] landmark blocks of each partition
+    // the same two ranges by value (kernel arguments), for the restart test
+    int pcb[kMaxPart + 1], plb[kMaxPart + 1];
     const int* lmblock_part;  // [nLmBlocks] partition of each landmark block
     const int* cam_ext;       // internal -> caller camera index
     const int* lm_ext;        // internal -> caller landmark index

@@ -282,33 +282,41 @@ __device__ __forceinline__ double next_gamma(const Params& p, double s, double* 
 // and the next Nesterov state.  Flags (1: the partition restarts, i.e. keeps
 // the plain MM candidate) and F shares go to s_rs / s_Fsh.  kp may be -1.
 __device__ void part_sums(const Params& p, int a, int lane, double* c, double* l) {
-    for (int q = p.part_camblk[a] + lane; q < p.part_camblk[a + 1]; q += kWave) {
+    for (int q = p.pcb[a] + lane; q < p.pcb[a + 1]; q += kWave) {
         const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)q * 4);
         c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
     }
-    for (int q = p.part_lmblk[a] + lane; q < p.part_lmblk[a + 1]; q += kWave) {
+    for (int q = p.plb[a] + lane; q < p.plb[a + 1]; q += kWave) {
         const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)q * 2);
         l[0] += v.x; l[1] += v.y;
     }
 }
 
-__device__ void test_one(const Params& p, int kp, bool writer, int a, const double* c, const double* l, int* s_rs,
-                         double* s_Fsh) {
+// Per-partition inputs of the test, loaded in the same round as the sums.
+struct TestLds {
+    double E[kMaxPart], EE[kMaxPart], Fbar[kMaxPart], col0[kMaxPart], col1[kMaxPart];
+    double s;
+    int64_t k;
+    int rs[kMaxPart];
+    double Fsh[kMaxPart];
+};
+
+__device__ void test_one(const Params& p, int kp, bool writer, int a, const double* c, const double* l, TestLds& d) {
     const int S = p.S;
-    const int cur = (kp & 1) * S, nxt = ((kp + 1) & 1) * S;
+    const int nxt = ((kp + 1) & 1) * S;
     // E^a(x^k | x^k): each pair's F split in halves between its sides
-    const double Fsh = c[2] + p.colsum[a];
+    const double Fsh = c[2] + d.col0[a];
     // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
-    const double V = Fsh + c[3] + p.colsum[S + a];
-    const double Fk = p.E[cur + a] + V - p.EE[cur + a];               // eq. Fak
-    const double Fb = (1.0 - p.eta) * p.Fbar[cur + a] + p.eta * Fk;   // eq. lFak
+    const double V = Fsh + c[3] + d.col1[a];
+    const double Fk = d.E[a] + V - d.EE[a];                        // eq. Fak
+    const double Fb = (1.0 - p.eta) * d.Fbar[a] + p.eta * Fk;      // eq. lFak
     const double dmm = c[0] + l[0], dacc = c[1] + l[1];
-    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                     // eq. Eak test
+    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                  // eq. Eak test
     if (p.accelerate && (p.flags & 1)) rs = 0;
     if (p.accelerate && (p.flags & 2)) rs = 1;
     const double dch = rs ? dmm : dacc;
-    s_rs[a] = rs;
-    s_Fsh[a] = Fsh;
+    d.rs[a] = rs;
+    d.Fsh[a] = Fsh;
     if (writer) {
         p.Fprev[nxt + a] = Fk;
         p.Fbar[nxt + a] = Fb;
@@ -322,14 +330,30 @@ __device__ void test_one(const Params& p, int kp, bool writer, int a, const doub
     }
 }
 
-__device__ void restart_test_block(const Params& p, int kp, bool writer, int* s_rs, double* s_Fsh) {
+__device__ void restart_test_block(const Params& p, int kp, bool writer, TestLds& d) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int S = p.S;
-    for (int a0 = wv; a0 < S; a0 += 8) {
-        const int a1 = a0 + 4;
-        double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
-        part_sums(p, a0, lane, c0, l0);
+    const int cur = (kp & 1) * S;
+    const int tid = threadIdx.x;
+    if (tid < S) {
+        d.E[tid] = p.E[cur + tid];
+        d.EE[tid] = p.EE[cur + tid];
+        d.Fbar[tid] = p.Fbar[cur + tid];
+        d.col0[tid] = p.colsum[tid];
+        d.col1[tid] = p.colsum[S + tid];
+    }
+    if (tid == kWave) {
+        d.s = p.st[kp & 1].s;
+        d.k = p.st[kp & 1].k;
+    }
+    double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
+    // the same number of rounds in every wave (the barrier inside is reached
+    // by all of them)
+    const int rounds = (S + 7) / 8;
+    for (int r = 0; r < rounds; ++r) {
+        const int a0 = wv + 8 * r, a1 = a0 + 4;
+        if (a0 < S) part_sums(p, a0, lane, c0, l0);
         if (a1 < S) part_sums(p, a1, lane, c1, l1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -341,21 +365,24 @@ __device__ void restart_test_block(const Params& p, int kp, bool writer, int* s_
             l0[q] = wave_sum(l0[q]);
             l1[q] = wave_sum(l1[q]);
         }
+        __syncthreads();  // the per-partition inputs are in LDS
         if (lane == 0) {
-            test_one(p, kp, writer, a0, c0, l0, s_rs, s_Fsh);
-            if (a1 < S) test_one(p, kp, writer, a1, c1, l1, s_rs, s_Fsh);
+            if (a0 < S) test_one(p, kp, writer, a0, c0, l0, d);
+            if (a1 < S) test_one(p, kp, writer, a1, c1, l1, d);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c0[q] = c1[q] = 0.0;
+        l0[0] = l0[1] = l1[0] = l1[1] = 0.0;
     }
     __syncthreads();
     if (writer && threadIdx.x == 0) {
         double F = 0.0;
-        for (int a = 0; a < S; ++a) F += s_Fsh[a];
-        const DevState& sc = p.st[kp & 1];
+        for (int a = 0; a < S; ++a) F += d.Fsh[a];
         double s1;
-        const double gam = next_gamma(p, sc.s, &s1);
+        const double gam = next_gamma(p, d.s, &s1);
         if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
-        const int64_t kk = sc.k;
-        if (kk >= 0) p.trace[kk % p.trace_cap] = F;
+        const int64_t kk = d.k;
+        if (kk >= 0) p.trace[kk & (int64_t)(p.trace_cap - 1)] = F;
         DevState& sn = p.st[(kp + 1) & 1];
         sn.F = F;
         sn.s = s1;
@@ -368,10 +395,9 @@ __device__ void restart_test_block(const Params& p, int kp, bool writer, int* s_
 // already stored (after daba_create, daba_set_state or a previous call).
 // One block.
 __global__ __launch_bounds__(256) void k_decide(Params p, int k) {
-    __shared__ int s_rs[kMaxPart];
-    __shared__ double s_Fsh[kMaxPart];
+    __shared__ TestLds d;
     if (p.st[0].decided) return;
-    restart_test_block(p, k - 1, true, s_rs, s_Fsh);
+    restart_test_block(p, k - 1, true, d);
 }
 
 // The restart flags of iteration k - 1 as a bit mask (stored by k_decide).
@@ -1389,11 +1415,10 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
 // candidate slots and the camera generation k % 3, so that x^k is stored
 // plainly whichever slot is read.
 __global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
-    __shared__ int s_rs[kMaxPart];
-    __shared__ double s_Fsh[kMaxPart];
-    restart_test_block(p, k - 1, blockIdx.x == 0, s_rs, s_Fsh);
+    __shared__ TestLds d;
+    restart_test_block(p, k - 1, blockIdx.x == 0, d);
     uint64_t restart = 0;
-    for (int a = 0; a < p.S; ++a) restart |= (uint64_t)(s_rs[a] != 0) << a;
+    for (int a = 0; a < p.S; ++a) restart |= (uint64_t)(d.rs[a] != 0) << a;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.st[0].decided = 1;
     const int par = (k + 1) & 1;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
