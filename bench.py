@@ -5,7 +5,7 @@ synthetic problem.  Default workload: 1,000 cameras, 200,000 landmarks,
 ~1.6M observations, 8 camera partitions, Huber loss, FP64 (the configuration
 the headline metric is quoted on).  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload C2]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cam1k-lm200k]
                   [--no-cpu-baseline] [--no-fp32] [--copy-calibration MB]
 """
 
@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="cam1k-lm200k")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")

@@ -36,19 +36,24 @@ IMAGE_HALF = (320.0, 240.0)
 
 # name -> (cameras, landmarks, track model, partitions, iterations, precision)
 CONFIGS = {
-    "C1": dict(n_cameras=50, n_landmarks=5_000, track="fixed8", n_partitions=1,
-               iterations=100, precision="fp64"),
-    "C2": dict(n_cameras=1_000, n_landmarks=200_000, track="fixed8", n_partitions=8,
-               iterations=200, precision="fp64"),
-    "C3": dict(n_cameras=5_000, n_landmarks=2_000_000, track="fixed8", n_partitions=16,
-               iterations=200, precision="fp32_mixed"),
-    "C4": dict(n_cameras=1_000, n_landmarks=200_000, track="fixed8", n_partitions=8,
-               iterations=0, precision="fp64"),
-    "C5": dict(n_cameras=20_000, n_landmarks=10_000_000, track="geom6", n_partitions=64,
-               iterations=300, precision="fp32_mixed"),
+    # 50 cameras, 5,000 landmarks, ~40k observations
+    "cam50-lm5k": dict(n_cameras=50, n_landmarks=5_000, track="fixed8", n_partitions=1,
+                       iterations=100, precision="fp64"),
+    # 1,000 cameras, 200,000 landmarks, ~1.6M observations
+    "cam1k-lm200k": dict(n_cameras=1_000, n_landmarks=200_000, track="fixed8", n_partitions=8,
+                         iterations=200, precision="fp64"),
+    # 5,000 cameras, 2,000,000 landmarks, ~16M observations
+    "cam5k-lm2m": dict(n_cameras=5_000, n_landmarks=2_000_000, track="fixed8", n_partitions=16,
+                       iterations=200, precision="fp32_mixed"),
+    # the 1.6M-observation shape with another seed (gradient checks)
+    "cam1k-lm200k-grad": dict(n_cameras=1_000, n_landmarks=200_000, track="fixed8", n_partitions=8,
+                              iterations=0, precision="fp64"),
+    # 20,000 cameras, 10,000,000 landmarks, ~60M observations (tracks 2 + Geometric(1/5))
+    "cam20k-lm10m": dict(n_cameras=20_000, n_landmarks=10_000_000, track="geom6", n_partitions=64,
+                         iterations=300, precision="fp32_mixed"),
 }
 
-_CONFIG_SEED = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
+_CONFIG_SEED = {"cam50-lm5k": 1, "cam1k-lm200k": 2, "cam5k-lm2m": 3, "cam1k-lm200k-grad": 4, "cam20k-lm10m": 5}
 
 
 def _rotation_exp(w: np.ndarray) -> np.ndarray:
@@ -181,7 +186,7 @@ def _choose_tracks(rng, R, t, d, lm, want):
             np.concatenate(uvs))
 
 
-def make_problem(config: str = "C1", seed: int | None = None, *, n_cameras=None,
+def make_problem(config: str = "cam50-lm5k", seed: int | None = None, *, n_cameras=None,
                  n_landmarks=None, track=None, n_partitions=None, outlier_rate=0.05,
                  pixel_sigma=1.0, rot_perturb=0.05, trans_perturb=0.1,
                  point_perturb=0.1, shuffle=True):

@@ -37,7 +37,7 @@ def _opts(**kw):
 
 @pytest.fixture(scope="module")
 def prob():
-    return make_problem("C1", n_cameras=12, n_landmarks=300, seed=21)
+    return make_problem("cam50-lm5k", n_cameras=12, n_landmarks=300, seed=21)
 
 
 def test_exports_every_declared_function():
@@ -55,7 +55,7 @@ def test_workspace_bytes_on_host(prob):
     n64 = B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts()))
     n32 = B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts(precision=1)))
     assert n64 > 0 and n32 > n64  # the mixed form keeps FP32 copies besides the FP64 state
-    big = make_problem("C1", n_cameras=12, n_landmarks=900, seed=21)
+    big = make_problem("cam50-lm5k", n_cameras=12, n_landmarks=900, seed=21)
     st2, _k2 = _problem(big)
     assert B.lib.daba_workspace_bytes(C.byref(st2), C.byref(_opts())) > n64
     assert B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts(eta=0.0))) == 0

@@ -37,7 +37,7 @@ def from_params(q):
 
 @pytest.fixture(scope="module")
 def sub():
-    big = make_problem("C4", n_cameras=40, n_landmarks=3000, seed=44)
+    big = make_problem("cam1k-lm200k-grad", n_cameras=40, n_landmarks=3000, seed=44)
     return subproblem(big, 10, 200)
 
 
@@ -87,7 +87,7 @@ def test_autograd_matches_central_differences(sub, loss):
 
 
 def test_gradcheck_tiny():
-    big = make_problem("C1", n_cameras=3, n_landmarks=20, seed=45)
+    big = make_problem("cam50-lm5k", n_cameras=3, n_landmarks=20, seed=45)
     sol = P.DabaSolver(big, loss="huber", n_partitions=1)
     # pixels in units of 1/512 px so every input is O(1)-scaled for gradcheck
     q = dev(to_params(big["cameras"])).requires_grad_(True)
@@ -115,7 +115,7 @@ def test_fp32_gradient_error(sub):
 def test_gradient_parity_differentiation_form():
     """Full differentiation-form size: 1,000 cameras, 200,000 landmarks,
     ~1.6M observations, against the oracle's gradient."""
-    prob = make_problem("C4")
+    prob = make_problem("cam1k-lm200k-grad")
     g = P.DabaSolver(prob, loss="huber", n_partitions=8)
     o = Oracle(prob, loss="huber", n_partitions=8)
     gc, gl, gu = (t.cpu().numpy() for t in g.grad())

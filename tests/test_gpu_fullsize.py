@@ -19,7 +19,7 @@ P = pytest.importorskip("paper_2305_07026_amd")
 
 @pytest.fixture(scope="module")
 def c2():
-    return make_problem("C2")
+    return make_problem("cam1k-lm200k")
 
 
 def test_fullsize_objective_and_one_step(c2):

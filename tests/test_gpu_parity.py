@@ -35,14 +35,14 @@ def nrel(a, b):
 @pytest.fixture(scope="module")
 def c1():
     # the small configuration: 50 cameras, 5000 landmarks, ~40k observations
-    return make_problem("C1")
+    return make_problem("cam50-lm5k")
 
 
 @pytest.fixture(scope="module")
 def tiled():
     # few cameras with many observations each (several tiles per camera and a
     # ragged tail) and geometric track lengths (many landmark groups)
-    return make_problem("C1", n_cameras=7, n_landmarks=2500, track="geom6", seed=31)
+    return make_problem("cam50-lm5k", n_cameras=7, n_landmarks=2500, track="geom6", seed=31)
 
 
 def both(prob, **kw):
@@ -196,7 +196,7 @@ def test_edge_cases_empty_entities():
     """A landmark nobody observes, a camera with no observations, more
     partitions than non-empty camera blocks, and a problem with no
     observations at all."""
-    prob = make_problem("C1", n_cameras=9, n_landmarks=200, seed=41)
+    prob = make_problem("cam50-lm5k", n_cameras=9, n_landmarks=200, seed=41)
     keep = prob["obs_camera"] != 4
     prob2 = dict(prob)
     prob2["obs_camera"] = prob["obs_camera"][keep]

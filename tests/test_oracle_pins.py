@@ -26,12 +26,12 @@ def _exp(w):
 
 @pytest.fixture(scope="module")
 def small():
-    return make_problem("C1", n_landmarks=400, seed=11)
+    return make_problem("cam50-lm5k", n_landmarks=400, seed=11)
 
 
 @pytest.fixture(scope="module")
 def tiny():
-    return make_problem("C1", n_cameras=6, n_landmarks=40, seed=12)
+    return make_problem("cam50-lm5k", n_cameras=6, n_landmarks=40, seed=12)
 
 
 # --------------------------------------------------------------- Sec. III
