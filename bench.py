@@ -45,6 +45,21 @@ def obs_pass_bytes(sol, layout_T: int, fp32: bool, accelerate: bool) -> float:
     return per_obs * sol.K + per_tile * layout_T
 
 
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per launch of the observation pass from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated against a device
+    copy), if they were taken on the kernel source as it is now; else None."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", f"k_obs_traffic_{workload}_{precision}.json")
+    src = os.path.join(ROOT, "paper_2305_07026_amd", "csrc", "daba_kernels.hip")
+    if not os.path.exists(rec):
+        return None
+    t = json.load(open(rec))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["kernel_source_sha256"]:
+        return None
+    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+
+
 def n_tiles(prob) -> int:
     cnt = __import__("numpy").bincount(prob["obs_camera"], minlength=prob["n_cameras"])
     return int(sum(-(-int(c) // 1024) for c in cnt))
@@ -177,10 +192,9 @@ def main():
                    "n_partitions": S, "precision": args.precision},
         "roofline": {"bound": "hbm", "kernel": "k_obs (observation pass)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": nbytes,
-                     "avg_launch_ms": kern[0]},
-        "kernel_ms_per_step": {"k_obs": kern[0], "k_entity": kern[1]},
-        "k_finalize_ms_per_call": kern[2] * args.steps,
+                     "traffic": measured_traffic(args.workload, args.precision),
+                     "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": kern[0]},
+        "kernel_ms_per_step": {"k_obs": kern[0], "k_entity": kern[1], "k_decide (+k_finalize once)": kern[2]},
         "wall_s_timed_region": wall,
         "setup_s": setup_s,
         "F_after": F_final,

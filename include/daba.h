@@ -139,11 +139,11 @@ int daba_set_state(daba_handle *h, const double *cams, const double *lms, const 
 int daba_get_metrics(daba_handle *h, double *metrics);
 
 /* Timing hook for measurement: runs n_iters iterations and returns, through
- * ms_out (host [3]), the summed GPU time in ms of the observation passes
- * (each begins with the previous iteration's restart test), of the camera and
- * landmark subproblems, and of the closing restart test that stores the
- * final iterate (once per call), measured with HIP events on the handle's
- * stream around each launch.  Synchronizes. */
+ * ms_out (host [3]), the summed GPU time in ms of the observation passes, of
+ * the camera and landmark subproblems, and of the restart tests (one small
+ * launch per iteration) together with the closing launch that stores the
+ * final iterate, measured with HIP events on the handle's stream around each
+ * launch.  Synchronizes. */
 int daba_iterate_timed(daba_handle *h, int n_iters, double *ms_out);
 
 /* Releases the handle (host memory only; the workspace stays the caller's). */

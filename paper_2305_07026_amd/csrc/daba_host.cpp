@@ -701,16 +701,17 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
 }
 
 // One iteration on stream s: the restart test of the previous iteration (one
-// block), the observation pass, the entity solves; ev (optional, 3 events)
-// brackets the first two together and the entity solves.
+// block), the observation pass, the entity solves; ev (optional, 4 events)
+// brackets each launch.
 static void launch_iteration(daba_handle* h, int k, hipStream_t s, hipEvent_t* ev = nullptr) {
     const Params& p = h->p;
     if (ev) hipcheck(hipEventRecord(ev[0], s), "event");
     hipcheck(launch_decide(p, k, s), "k_decide");
-    hipcheck(launch_obs_pass(p, k, s), "k_obs");
     if (ev) hipcheck(hipEventRecord(ev[1], s), "event");
-    hipcheck(launch_entity(p, k, s), "k_entity");
+    hipcheck(launch_obs_pass(p, k, s), "k_obs");
     if (ev) hipcheck(hipEventRecord(ev[2], s), "event");
+    hipcheck(launch_entity(p, k, s), "k_entity");
+    if (ev) hipcheck(hipEventRecord(ev[3], s), "event");
 }
 
 // Captures iterations with k mod 6 = 0..5 once; replaying the graph runs one
@@ -739,19 +740,22 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     std::vector<hipEvent_t> ev;
     hipEvent_t fin[2] = {nullptr, nullptr};
     int pooled = 0;
+    // ms[0]: observation passes, ms[1]: entity solves, ms[2]: restart tests
+    // (one per iteration) and the closing k_finalize
     auto drain = [&]() {
         if (pooled == 0) return;
-        hipcheck(hipEventSynchronize(ev[3 * (pooled - 1) + 2]), "event sync");
+        hipcheck(hipEventSynchronize(ev[4 * (pooled - 1) + 3]), "event sync");
+        constexpr int slot[3] = {2, 0, 1};
         for (int q = 0; q < pooled; ++q)
-            for (int e = 0; e < 2; ++e) {
+            for (int e = 0; e < 3; ++e) {
                 float t = 0.f;
-                hipcheck(hipEventElapsedTime(&t, ev[3 * q + e], ev[3 * q + e + 1]), "elapsed");
-                ms[e] += t;
+                hipcheck(hipEventElapsedTime(&t, ev[4 * q + e], ev[4 * q + e + 1]), "elapsed");
+                ms[slot[e]] += t;
             }
         pooled = 0;
     };
     if (ms) {
-        ev.resize(3 * kPool);
+        ev.resize(4 * kPool);
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
         for (auto& e : fin) hipcheck(hipEventCreate(&e), "hipEventCreate");
         for (int e = 0; e < 3; ++e) ms[e] = 0.0;
@@ -767,7 +771,7 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
                 continue;
             }
             const int k = (int)(h->k % 6);
-            launch_iteration(h, k, s, ms ? &ev[3 * pooled] : nullptr);
+            launch_iteration(h, k, s, ms ? &ev[4 * pooled] : nullptr);
             if (ms && ++pooled == kPool) drain();
             h->k++;
         }

@@ -106,7 +106,7 @@ class DabaSolver:
 
     def iterate_timed(self, n: int):
         """n iterations; returns summed GPU ms of (observation passes, entity
-        solves, the closing restart test of the call)."""
+        solves, restart tests and the closing store of the iterate)."""
         ms = np.zeros(3)
         self._chk(B.lib.daba_iterate_timed(self._h, n, _ptr(ms, C.c_double)), "daba_iterate_timed")
         return ms
