@@ -42,6 +42,27 @@ struct Layout {
     int T = 0, G = 0;
 };
 
+// Landmark-pass blocks of at most `per_block` consecutive groups of one
+// partition (one wave per group).
+void build_lm_blocks(Layout& L, int per_block) {
+    L.lmblock_g0.clear();
+    L.lmblock_g1.clear();
+    L.lmblock_part.clear();
+    L.part_lmblk.assign(L.S + 1, 0);
+    int g = 0;
+    for (int a = 0; a < L.S; ++a) {
+        L.part_lmblk[a] = (int)L.lmblock_g0.size();
+        int g0 = g;
+        while (g < L.G && L.lpart[L.lm_ext[L.group_lm0[g]]] == a) ++g;
+        for (int q = g0; q < g; q += per_block) {
+            L.lmblock_g0.push_back(q);
+            L.lmblock_g1.push_back(std::min(q + per_block, g));
+            L.lmblock_part.push_back(a);
+        }
+    }
+    L.part_lmblk[L.S] = (int)L.lmblock_g0.size();
+}
+
 std::string vformat(const char* fmt, va_list ap) {
     char buf[512];
     vsnprintf(buf, sizeof buf, fmt, ap);
@@ -203,7 +224,6 @@ void build_layout(const daba_problem* p, Layout& L) {
     L.T = (int)L.tile_cam.size();
     // camera-solve blocks and landmark-pass blocks, never straddling partitions
     L.part_camblk.assign(S + 1, 0);
-    L.part_lmblk.assign(S + 1, 0);
     for (int a = 0; a < S; ++a) {
         L.part_camblk[a] = (int)L.camblock_c0.size();
         for (int c = L.part_cam[a]; c < L.part_cam[a + 1]; c += kCamBlock) {
@@ -212,20 +232,7 @@ void build_layout(const daba_problem* p, Layout& L) {
         }
     }
     L.part_camblk[S] = (int)L.camblock_c0.size();
-    {
-        int g = 0;
-        for (int a = 0; a < S; ++a) {
-            L.part_lmblk[a] = (int)L.lmblock_g0.size();
-            int g0 = g;
-            while (g < L.G && L.lpart[L.lm_ext[L.group_lm0[g]]] == a) ++g;
-            for (int q = g0; q < g; q += kLmWaves) {
-                L.lmblock_g0.push_back(q);
-                L.lmblock_g1.push_back(std::min(q + kLmWaves, g));
-                L.lmblock_part.push_back(a);
-            }
-        }
-        L.part_lmblk[S] = (int)L.lmblock_g0.size();
-    }
+    build_lm_blocks(L, kLmWaves);
 }
 
 // Workspace carve-up: every array 256-byte aligned.
@@ -366,8 +373,8 @@ struct daba_handle {
     hipGraphExec_t period = nullptr;
     bool graphs = true;
     ~daba_handle() {
-        if (period) hipGraphExecDestroy(period);
-        if (cap_stream) hipStreamDestroy(cap_stream);
+        if (period) (void)hipGraphExecDestroy(period);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
 
@@ -612,6 +619,7 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         for (int a = 0; a <= L.S; ++a) {
             p.pcb[a] = L.part_camblk[a];
             p.plb[a] = L.part_lmblk[a];
+            p.pcam[a] = L.part_cam[a];
         }
         p.nLmBlocks = (int)L.lmblock_g0.size();
         p.loss = opt->loss;
@@ -725,7 +733,7 @@ static bool ensure_period_graph(daba_handle* h) {
     hipGraph_t g = nullptr;
     hipcheck(hipStreamEndCapture(h->cap_stream, &g), "hipStreamEndCapture");
     hipError_t e = hipGraphInstantiate(&h->period, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     hipcheck(e, "hipGraphInstantiate");
     return true;
 }

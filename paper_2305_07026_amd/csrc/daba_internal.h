@@ -87,8 +87,9 @@ struct Params {
     const int* camblock_c1;
     const int* part_camblk;   // [S+1] camera blocks of each partition
     const int* part_lmblk;    // [S+1] landmark blocks of each partition
-    // the same two ranges by value (kernel arguments), for the restart test
-    int pcb[kMaxPart + 1], plb[kMaxPart + 1];
+    // the same two ranges and the first camera of each partition by value
+    // (kernel arguments): a block finds its partition without a memory load
+    int pcb[kMaxPart + 1], plb[kMaxPart + 1], pcam[kMaxPart + 1];
     const int* lmblock_part;  // [nLmBlocks] partition of each landmark block
     const int* cam_ext;       // internal -> caller camera index
     const int* lm_ext;        // internal -> caller landmark index
@@ -125,6 +126,7 @@ struct Params {
     double2* tmp_uv;          // [K]
     double* grad_tile;        // [T * 16]
 };
+static_assert(sizeof(Params) <= 4096, "Params is passed as a kernel argument");
 
 // Launchers (daba_kernels.hip).  k mod 3 selects the camera generation and
 // k mod 2 the landmark pair buffer.

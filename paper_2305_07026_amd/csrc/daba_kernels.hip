@@ -282,13 +282,19 @@ __device__ __forceinline__ double next_gamma(const Params& p, double s, double* 
 // and the next Nesterov state.  Flags (1: the partition restarts, i.e. keeps
 // the plain MM candidate) and F shares go to s_rs / s_Fsh.  kp may be -1.
 __device__ void part_sums(const Params& p, int a, int lane, double* c, double* l) {
-    for (int q = p.pcb[a] + lane; q < p.pcb[a + 1]; q += kWave) {
-        const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)q * 4);
-        c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
-    }
-    for (int q = p.plb[a] + lane; q < p.plb[a + 1]; q += kWave) {
-        const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)q * 2);
-        l[0] += v.x; l[1] += v.y;
+    const int c0 = p.pcb[a], nc = p.pcb[a + 1] - c0, l0 = p.plb[a], nl = p.plb[a + 1] - l0;
+    const int n = nc > nl ? nc : nl;
+    // unrolled so that several rounds of loads are in flight together
+#pragma unroll 4
+    for (int q = lane; q < n; q += kWave) {
+        if (q < nc) {
+            const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)(c0 + q) * 4);
+            c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
+        }
+        if (q < nl) {
+            const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)(l0 + q) * 2);
+            l[0] += v.x; l[1] += v.y;
+        }
     }
 }
 
@@ -330,22 +336,28 @@ __device__ void test_one(const Params& p, int kp, bool writer, int a, const doub
     }
 }
 
-__device__ void restart_test_block(const Params& p, int kp, bool writer, TestLds& d) {
+// With skip_if_decided the block returns (before any store) when the test
+// is already stored; that flag is loaded together with every other input.
+__device__ void restart_test_block(const Params& p, int kp, bool writer, bool skip_if_decided, TestLds& d) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int S = p.S;
     const int cur = (kp & 1) * S;
     const int tid = threadIdx.x;
+    const int decided = skip_if_decided ? p.st[0].decided : 0;
+    double in[5] = {0, 0, 0, 0, 0};
     if (tid < S) {
-        d.E[tid] = p.E[cur + tid];
-        d.EE[tid] = p.EE[cur + tid];
-        d.Fbar[tid] = p.Fbar[cur + tid];
-        d.col0[tid] = p.colsum[tid];
-        d.col1[tid] = p.colsum[S + tid];
+        in[0] = p.E[cur + tid];
+        in[1] = p.EE[cur + tid];
+        in[2] = p.Fbar[cur + tid];
+        in[3] = p.colsum[tid];
+        in[4] = p.colsum[S + tid];
     }
+    double s_in = 0.0;
+    int64_t k_in = 0;
     if (tid == kWave) {
-        d.s = p.st[kp & 1].s;
-        d.k = p.st[kp & 1].k;
+        s_in = p.st[kp & 1].s;
+        k_in = p.st[kp & 1].k;
     }
     double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
     // the same number of rounds in every wave (the barrier inside is reached
@@ -364,6 +376,20 @@ __device__ void restart_test_block(const Params& p, int kp, bool writer, TestLds
         for (int q = 0; q < 2; ++q) {
             l0[q] = wave_sum(l0[q]);
             l1[q] = wave_sum(l1[q]);
+        }
+        if (r == 0) {
+            if (decided) return;  // uniform over the block
+            if (tid < S) {
+                d.E[tid] = in[0];
+                d.EE[tid] = in[1];
+                d.Fbar[tid] = in[2];
+                d.col0[tid] = in[3];
+                d.col1[tid] = in[4];
+            }
+            if (tid == kWave) {
+                d.s = s_in;
+                d.k = k_in;
+            }
         }
         __syncthreads();  // the per-partition inputs are in LDS
         if (lane == 0) {
@@ -396,8 +422,7 @@ __device__ void restart_test_block(const Params& p, int kp, bool writer, TestLds
 // One block.
 __global__ __launch_bounds__(256) void k_decide(Params p, int k) {
     __shared__ TestLds d;
-    if (p.st[0].decided) return;
-    restart_test_block(p, k - 1, true, d);
+    restart_test_block(p, k - 1, true, true, d);
 }
 
 // The restart flags of iteration k - 1 as a bit mask (stored by k_decide).
@@ -921,8 +946,11 @@ __device__ void grad_hess(const double* mom, const CamD& y, const CamD& c, doubl
                     xi * (c.d[k2] - y.d[k2]);
 }
 
-// (A) x = b for SPD A given as packed lower triangle; false if not SPD
+// (A) x = b for SPD A given as packed lower triangle; false if not SPD.
+// One division per pivot (its reciprocal); every other quotient is a
+// product, which keeps FP64 divisions off the solve's serial chain.
 __device__ bool chol9(double* L, const double* b, double* x) {
+    double inv[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
 #pragma unroll
@@ -932,9 +960,11 @@ __device__ bool chol9(double* L, const double* b, double* x) {
             for (int q = 0; q < j; ++q) s -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
             if (i == j) {
                 if (!(s > 0.0)) return false;
-                L[i * (i + 1) / 2 + i] = sqrt(s);
+                const double dj = sqrt(s);
+                L[i * (i + 1) / 2 + i] = dj;
+                inv[i] = 1.0 / dj;
             } else {
-                L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+                L[i * (i + 1) / 2 + j] = s * inv[j];
             }
         }
     }
@@ -944,14 +974,14 @@ __device__ bool chol9(double* L, const double* b, double* x) {
         double s = b[i];
 #pragma unroll
         for (int q = 0; q < i; ++q) s -= L[i * (i + 1) / 2 + q] * z[q];
-        z[i] = s / L[i * (i + 1) / 2 + i];
+        z[i] = s * inv[i];
     }
 #pragma unroll
     for (int i = 8; i >= 0; --i) {
         double s = z[i];
 #pragma unroll
         for (int q = i + 1; q < 9; ++q) s -= L[q * (q + 1) / 2 + i] * x[q];
-        x[i] = s / L[i * (i + 1) / 2 + i];
+        x[i] = s * inv[i];
     }
     return true;
 }
@@ -981,8 +1011,10 @@ __device__ __forceinline__ void exp_so3(const double* w, double* E) {
 // Levenberg-Marquardt on one camera's surrogate: start at y, mu = 1e-4,
 // accept iff the surrogate strictly decreases (mu /= 10), else mu *= 10,
 // give up after 10 rejects in a row; inner_steps accepted steps (<= 0:
-// until the step is negligible or 100 accepted steps).
-__device__ CamD lm_camera(const double* mom, const CamD& y, double xi, int inner_steps) {
+// until the step is negligible or 100 accepted steps).  *phi_out receives
+// Phi(result) - Phi(y), exactly as phi_delta computes it (0 if no step was
+// accepted).
+__device__ CamD lm_camera(const double* mom, const CamD& y, double xi, int inner_steps, double* phi_out) {
     CamD c = y;
     double phi = 0.0;
     double mu = 1e-4;
@@ -990,14 +1022,13 @@ __device__ CamD lm_camera(const double* mom, const CamD& y, double xi, int inner
     for (;;) {
         if (inner_steps > 0 && succ >= inner_steps) break;
         if (inner_steps <= 0 && succ >= 100) break;
-        double Hp[45], g[9];
-        grad_hess(mom, y, c, xi, Hp, g);
-        double A[45], rhs[9], dl[9];
-#pragma unroll
-        for (int i = 0; i < 45; ++i) A[i] = Hp[i];
+        // the model is rebuilt on every pass, so the damped matrix is formed
+        // in place from it
+        double A[45], g[9], rhs[9], dl[9];
+        grad_hess(mom, y, c, xi, A, g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            A[i * (i + 1) / 2 + i] += mu * Hp[i * (i + 1) / 2 + i];
+            A[i * (i + 1) / 2 + i] += mu * A[i * (i + 1) / 2 + i];
             rhs[i] = -g[i];
         }
         bool ok = chol9(A, rhs, dl);
@@ -1035,6 +1066,7 @@ __device__ CamD lm_camera(const double* mom, const CamD& y, double xi, int inner
             if (++rej >= 10) break;
         }
     }
+    *phi_out = phi;
     return c;
 }
 
@@ -1181,94 +1213,120 @@ __device__ void extrapolate_cam(const double* cn, const double* co, double gam, 
 }
 
 
+// Partition of block b from by-value block ranges (starts[a] = first block
+// of partition a, non-decreasing, starts[0] = 0): no memory load.
+__device__ __forceinline__ int block_partition(const int* starts, int S, int b) {
+    int a = 0;
+    for (int q = 1; q < S; ++q) a += (starts[q] <= b);
+    return a;
+}
+
+// LDS of a camera block: the accelerated candidates handed to the lanes of
+// the plain surrogate.
+struct CamLds {
+    double c[kCamBlock][16];
+};
+
+// Sum of one surrogate's moments over a camera's tiles (two tiles' loads in
+// flight at a time; the sums keep the tile order).  f receives the camera's
+// F and gap shares.
+__device__ __forceinline__ void camera_moments(const Params& p, int t0, int t1, int off, double* mom, double* f) {
+    int t = t0;
+    for (; t + 1 < t1; t += 2) {
+        const double* u = p.tile_vals + (size_t)t * kTileVals;
+        const double* v = u + kTileVals;
+        double x[kMom + 2], y[kMom + 2];
+#pragma unroll
+        for (int a = 0; a < kMom; ++a) {
+            x[a] = u[off + a];
+            y[a] = v[off + a];
+        }
+        x[kMom] = u[2 * kMom];
+        x[kMom + 1] = u[2 * kMom + 1];
+        y[kMom] = v[2 * kMom];
+        y[kMom + 1] = v[2 * kMom + 1];
+#pragma unroll
+        for (int a = 0; a < kMom; ++a) mom[a] = (mom[a] + x[a]) + y[a];
+        f[0] = (f[0] + x[kMom]) + y[kMom];
+        f[1] = (f[1] + x[kMom + 1]) + y[kMom + 1];
+    }
+    if (t < t1) {
+        const double* u = p.tile_vals + (size_t)t * kTileVals;
+#pragma unroll
+        for (int a = 0; a < kMom; ++a) mom[a] += u[off + a];
+        f[0] += u[2 * kMom];
+        f[1] += u[2 * kMom + 1];
+    }
+}
+
 // Camera subproblems of one block of <= 128 cameras in one partition:
 // threads [0,128) solve the plain surrogate, [128,256) the accelerated one.
+// The block's partition (and so the restart flag that picks x^k among the
+// candidates of iteration k - 1) comes from the kernel arguments, so the
+// moments and x^k are each one load away.  The plain surrogate's lane also
+// evaluates the plain surrogate at the accelerated candidate, which the
+// accelerated lane hands over through LDS.
 template <bool ACC>
-__device__ __forceinline__ void camera_role(const Params& p, int k, int b, double (*sred)[4]) {
+__device__ __forceinline__ void camera_role(const Params& p, int k, int b, CamLds& sh, double (*red)[4]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const double xi = p.xi;
     const int surr = threadIdx.x / kCamBlock;
-    const int ci = p.camblock_c0[b] + (threadIdx.x % kCamBlock);
-    double dv = 0.0, f1 = 0.0, f2 = 0.0;
-    if (ci < p.camblock_c1[b] && (surr == 0 || ACC)) {
-        double mom[kMom];
+    const int cl = threadIdx.x % kCamBlock;
+    const int a = block_partition(p.pcb, p.S, b);
+    const int ci = p.pcam[a] + (b - p.pcb[a]) * kCamBlock + cl;
+    const bool cam = ci < p.pcam[a + 1];
+    const int cc = p.restart[a] ? 0 : 1;  // x^k: the candidate chosen by the last restart test
+    double dv = 0.0, dacc = 0.0, f[2] = {0.0, 0.0};
+    double mom[kMom];
+    CamD ck;
+    if (cam && (surr == 0 || ACC)) {
+        const size_t o = (size_t)ci * kCamRec;
 #pragma unroll
-        for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
-        const int t0 = p.cam_tile_off[ci], t1 = p.cam_tile_off[ci + 1];
-        const int off = surr == 0 ? 0 : kMom;
-        for (int t = t0; t < t1; ++t) {
-            const double* tv = p.tile_vals + (size_t)t * kTileVals;
-#pragma unroll
-            for (int a = 0; a < kMom; ++a) mom[a] += tv[off + a];
-            f1 += tv[2 * kMom];
-            f2 += tv[2 * kMom + 1];
-        }
-        // x^k and x-bar^k: the candidates of iteration k - 1 chosen by its
-        // restart test (stored by k_obs or by the previous call)
-        const int cc = p.restart[p.cam_part[ci]] ? 0 : 1;
-        const CamD ck = load_camd(p.ccand[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
-        if (surr == 0) store_camd(p.cams[k % 3] + (size_t)ci * kCamRec, ck);
-        const CamD y = surr == 0 ? ck : load_camd(p.cbar[(k + 1) & 1][cc] + (size_t)ci * kCamRec);
-        const CamD c = lm_camera(mom, y, xi, p.inner_steps);
-        store_camd(p.ccand[k & 1][surr] + (size_t)ci * kCamRec, c);
+        for (int q = 0; q < kMom; ++q) mom[q] = 0.0;
+        camera_moments(p, p.cam_tile_off[ci], p.cam_tile_off[ci + 1], surr == 0 ? 0 : kMom, mom, f);
+        ck = load_camd(p.ccand[(k + 1) & 1][cc] + o);
+        if (surr == 0) store_camd(p.cams[k % 3] + o, ck);
+        const CamD y = surr == 0 ? ck : load_camd(p.cbar[(k + 1) & 1][cc] + o);
+        double phi;
+        const CamD c = lm_camera(mom, y, xi, p.inner_steps, &phi);
+        store_camd(p.ccand[k & 1][surr] + o, c);
         if constexpr (ACC) {
             // the extrapolation the next iteration uses if this candidate is
             // chosen; gamma^(k+1) depends only on s^(k), so it is known now
             double s1;
             const double gnext = next_gamma(p, p.st[k & 1].s, &s1);
-            double cn[16], cbar[16];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) cn[a] = c.R[a];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cn[9 + a] = c.t[a];
-                cn[12 + a] = c.d[a];
-            }
-            cn[15] = 0.0;
-            double cko[16];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) cko[a] = ck.R[a];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cko[9 + a] = ck.t[a];
-                cko[12 + a] = ck.d[a];
-            }
-            cko[15] = 0.0;
+            double cn[16], cko[16], cbar[16];
+            store_camd(cn, c);
+            store_camd(cko, ck);
             extrapolate_cam(cn, cko, gnext, cbar);
-            double* dst = p.cbar[k & 1][surr] + (size_t)ci * kCamRec;
+            double* dst = p.cbar[k & 1][surr] + o;
 #pragma unroll
-            for (int a = 0; a < 16; ++a) dst[a] = cbar[a];
+            for (int q = 0; q < 16; ++q) dst[q] = cbar[q];
+            if (surr == 1) store_camd(sh.c[cl], c);
         }
-        if (surr == 1) {
-            // the plain surrogate (about x^k) at the accelerated candidate
-#pragma unroll
-            for (int a = 0; a < kMom; ++a) mom[a] = 0.0;
-            for (int t = t0; t < t1; ++t) {
-                const double* tv = p.tile_vals + (size_t)t * kTileVals;
-#pragma unroll
-                for (int a = 0; a < kMom; ++a) mom[a] += tv[a];
-            }
-        }
-        dv = phi_delta(mom, ck, c, xi);
-        if (surr == 1) f1 = f2 = 0.0;
+        // about y = x^k, the accepted change is the plain surrogate's change
+        if (surr == 0) dv = phi;
+        else f[0] = f[1] = 0.0;
+    }
+    if constexpr (ACC) {
+        __syncthreads();  // the accelerated candidates are in LDS
+        if (cam && surr == 0) dacc = phi_delta(mom, ck, load_camd(sh.c[cl]), xi);
     }
     // block sums in a fixed order: (dmm, dacc, F share, gap share)
-    double v0 = surr == 0 ? dv : 0.0, v1 = surr == 1 ? dv : 0.0;
-    v0 = wave_sum(v0);
-    v1 = wave_sum(v1);
-    f1 = wave_sum(f1);
-    f2 = wave_sum(f2);
+    double v0 = wave_sum(dv), v1 = wave_sum(dacc);
+    f[0] = wave_sum(f[0]);
+    f[1] = wave_sum(f[1]);
     if (lane == 0) {
-        sred[wv][0] = v0;
-        sred[wv][1] = v1;
-        sred[wv][2] = f1;
-        sred[wv][3] = f2;
+        red[wv][0] = v0;
+        red[wv][1] = v1;
+        red[wv][2] = f[0];
+        red[wv][3] = f[1];
     }
     __syncthreads();
     if (threadIdx.x < 4) {
         double s = 0.0;
-        for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
+        for (int w = 0; w < 4; ++w) s += red[w][threadIdx.x];
         p.camblk_vals[(size_t)b * 4 + threadIdx.x] = s;
     }
 }
@@ -1323,35 +1381,14 @@ __device__ __forceinline__ void write_cand_pair(const Params& p, int k, int cand
     }
 }
 
-// One launch, three kinds of blocks: camera subproblems, landmark subproblems
-// (one wave per group of landmarks with equal track length), and column sums
-// of the per-tile partition bins.  The roles are independent, so the camera
-// solves (long serial chains on few threads) overlap the landmark pass.
+// Landmark subproblems of one block: one wave per group of equal track
+// length, one lane per landmark (the records it reads are consecutive
+// across the wave's lanes).
 template <typename RT, bool ACC>
-__global__ __launch_bounds__(256) void k_entity(Params p, int k) {
-    __shared__ double sred[4][4];
+__device__ __forceinline__ void landmark_role(const Params& p, int k, int lb, double (*sred)[4]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const double xi = p.xi;
-    if ((int)blockIdx.x < p.nCamBlocks) {
-        camera_role<ACC>(p, k, blockIdx.x, sred);
-        return;
-    }
-    const int lb = blockIdx.x - p.nCamBlocks;
-    if (lb >= p.nLmBlocks) {
-        // column sums of the per-tile partition bins
-        const int col = lb - p.nLmBlocks;
-        const double* src = p.tile_bins + (size_t)col * p.T;
-        double s = 0.0;
-        for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
-        s = wave_sum(s);
-        if (lane == 0) sred[wv][0] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) p.colsum[col] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
-        return;
-    }
-    // ---- landmark subproblems: one wave per group of equal track length
-    if (blockIdx.x == (unsigned)p.nCamBlocks && threadIdx.x == 0) p.st[0].decided = 0;
     const int g = p.lmblock_g0[lb] + wv;
     // l^k and l^(k-1): the candidate of iteration k - 1 chosen for this
     // block's partition
@@ -1408,6 +1445,38 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
     }
 }
 
+// One launch, three kinds of blocks: camera subproblems, column sums of the
+// per-tile partition bins, and landmark subproblems (in that order, so that
+// the short column sums are not queued behind the landmark blocks).  The
+// roles are independent, so the camera solves (long serial chains on few
+// threads) overlap the landmark pass.
+template <typename RT, bool ACC>
+__global__ __launch_bounds__(256) void k_entity(Params p, int k) {
+    __shared__ CamLds sh;
+    __shared__ double sred[4][4];  // block reductions
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    if ((int)blockIdx.x < p.nCamBlocks) {
+        camera_role<ACC>(p, k, blockIdx.x, sh, sred);
+        return;
+    }
+    const int cb = blockIdx.x - p.nCamBlocks;
+    if (cb < 2 * p.S) {
+        // column sums of the per-tile partition bins
+        const double* src = p.tile_bins + (size_t)cb * p.T;
+        double s = 0.0;
+        for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
+        s = wave_sum(s);
+        if (lane == 0) sred[wv][0] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) p.colsum[cb] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+        return;
+    }
+    const int lb = cb - 2 * p.S;
+    if (lb == 0 && threadIdx.x == 0) p.st[0].decided = 0;
+    landmark_role<RT, ACC>(p, k, lb, sred);
+}
+
 // ------------------------------------------------------- select and roll
 
 // End of a call, after iteration k - 1: its restart test (every block takes
@@ -1416,7 +1485,7 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
 // plainly whichever slot is read.
 __global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
     __shared__ TestLds d;
-    restart_test_block(p, k - 1, blockIdx.x == 0, d);
+    restart_test_block(p, k - 1, blockIdx.x == 0, false, d);
     uint64_t restart = 0;
     for (int a = 0; a < p.S; ++a) restart |= (uint64_t)(d.rs[a] != 0) << a;
     if (blockIdx.x == 0 && threadIdx.x == 0) p.st[0].decided = 1;
