@@ -6,7 +6,7 @@ synthetic problem.  Default workload: 1,000 cameras, 200,000 landmarks,
 the headline metric is quoted on).  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cam1k-lm200k]
-                  [--no-cpu-baseline] [--no-fp32] [--copy-calibration MB]
+                  [--no-cpu-baseline] [--no-fp32] [--no-attainable] [--copy-calibration MB]
 """
 
 from __future__ import annotations
@@ -89,21 +89,56 @@ def equal_objective(prob, ms64, ms32, iters, S, make):
     return out
 
 
-def cpu_baseline(prob, S, budget_s=15.0):
+def cpu_baseline(prob, S, budget_s=15.0, budget_1t_s=6.0):
     """The oracle, as it stands, on the same problem and options: whole
-    iterations from x^0 until about budget_s of CPU work has been done."""
-    from oracle import Oracle, num_threads
+    iterations from x^0 until about budget_s of CPU work has been done on
+    every host core, then (continuing from there) about budget_1t_s on one
+    thread."""
+    from oracle import Oracle, num_threads, set_num_threads
     o = Oracle(prob, n_partitions=S, loss="huber", delta=1.0, xi=1e-9, eta=0.5)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        o.iterate(1)
-        n += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s or n >= 200:
-            break
-    return dict(value=prob["n_obs"] * n / dt, unit="obs*iter/s", cores=num_threads(), kind="oracle",
+
+    def run(budget):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            o.iterate(1)
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget or n >= 200:
+                return n, dt
+
+    cores = num_threads()
+    n, dt = run(budget_s)
+    set_num_threads(1)
+    n1, dt1 = run(budget_1t_s)
+    set_num_threads(0)
+    return dict(value=prob["n_obs"] * n / dt, unit="obs*iter/s", cores=cores, kind="oracle",
                 sample=f"{n} oracle iteration(s) of the same {prob['n_obs']}-observation problem from x^0, "
-                       f"{dt:.1f} s wall, OpenMP over entities")
+                       f"{dt:.1f} s wall, OpenMP over entities",
+                value_1thread=prob["n_obs"] * n1 / dt1,
+                sample_1thread=f"the next {n1} iteration(s) on 1 thread, {dt1:.1f} s wall")
+
+
+def attainable_bandwidth(mib=1024, reps=10):
+    """HBM bandwidth a plain device-to-device copy reaches on this GPU (read
+    + write bytes per second), the practical ceiling next to the vendor
+    peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def main():
@@ -117,6 +152,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy of this many MiB (for HBM counter calibration)")
+    ap.add_argument("--no-attainable", action="store_true",
+                    help="skip the copy-bandwidth measurement (implied by --copy-calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU path is not "
@@ -162,6 +199,14 @@ def main():
     gpu_ms = e0.elapsed_time(e1)
     ms_per_step = gpu_ms / args.steps
     value = K * args.steps / (gpu_ms / 1e3)
+    # two more timed regions of the same length, for the spread
+    repeats = [ms_per_step]
+    for _ in range(2):
+        e0.record(stream)
+        sol.iterate(args.steps, trace=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        repeats.append(e0.elapsed_time(e1) / args.steps)
 
     # per-kernel durations from HIP events around each launch, over the same
     # number of steps of the same run (instrumented launches, no graph)
@@ -171,6 +216,10 @@ def main():
     nbytes = obs_pass_bytes(sol, T, fp32, True)
     achieved = nbytes / (kern[0] / 1e3) / 1e9
     F_final = sol.objective()
+    attainable = None
+    if not (args.no_attainable or args.copy_calibration):
+        log("copy bandwidth")
+        attainable = attainable_bandwidth()
 
     out = {
         "metric": "observation-iterations/s and HBM GB/s (FP32-mixed vs FP64) at equal final objective",
@@ -190,11 +239,15 @@ def main():
                                f"adaptive restart), 1 inner LM step, {args.precision}",
                    "n_cameras": prob["n_cameras"], "n_landmarks": prob["n_landmarks"], "n_obs": K,
                    "n_partitions": S, "precision": args.precision},
-        "roofline": {"bound": "hbm", "kernel": "k_obs (observation pass)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_obs_dma (observation pass)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, args.precision),
-                     "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": kern[0]},
-        "kernel_ms_per_step": {"k_obs": kern[0], "k_entity": kern[1], "k_decide (+k_finalize once)": kern[2]},
+                     "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": kern[0],
+                     "attainable_copy_GBs": attainable,
+                     "frac_of_attainable": achieved / attainable if attainable else None},
+        "ms_per_step_repeats": repeats,
+        "ms_per_step_median": sorted(repeats)[1],
+        "kernel_ms_per_step": {"k_obs_dma": kern[0], "k_entity": kern[1], "k_decide (+k_finalize once)": kern[2]},
         "wall_s_timed_region": wall,
         "setup_s": setup_s,
         "F_after": F_final,

@@ -48,6 +48,7 @@ def _load():
     lib.orc_projrot3d.argtypes = [pd, pd]
     lib.orc_cams_to_internal.argtypes = [C.c_void_p, pd, pd, i64]
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_num_threads.argtypes = [C.c_int]
     _lib = lib
     return lib
 
@@ -79,6 +80,11 @@ def projrot3d(M):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP loops (n < 1: one per processor)."""
+    _load().orc_set_num_threads(int(n))
 
 
 class Oracle:

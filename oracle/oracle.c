@@ -507,6 +507,14 @@ int orc_num_threads(void) {
 #endif
 }
 
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 void orc_destroy(orc_state *st) {
     if (!st) return;
     free(st->cam); free(st->lmk); free(st->u); free(st->cpart); free(st->lpart);

@@ -116,7 +116,11 @@ int orc_projrot3d(const double *M, double *R);
 /* Internal <-> caller unit conversion of a camera array [M*15]. */
 int orc_cams_to_internal(const orc_state *st, const double *in, double *out, int64_t M);
 
+/* Threads of the OpenMP loops over entities: the current count, and a new
+ * one (n < 1: one per processor).  The arithmetic and its order do not
+ * depend on the count. */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }
