@@ -103,11 +103,20 @@ def _project(R, t, d, lm):
     rho = nxy / zs
     d1, d2, d3 = d[:, 0], d[:, 1], d[:, 2]
     r = rho * d1
+    # 30 Newton steps; an entry whose step is exactly zero stays where it is
+    # for every later step, so only the others are iterated further
+    act = np.arange(r.size)
     for _ in range(30):
-        r2 = r * r
-        g = r - rho * (d1 + d2 * r2 + d3 * r2 * r2)
-        dg = 1.0 - rho * (2.0 * d2 * r + 4.0 * d3 * r2 * r)
-        r = r - g / dg
+        ra, pa = r[act], rho[act]
+        a1, a2, a3 = d1[act], d2[act], d3[act]
+        r2 = ra * ra
+        g = ra - pa * (a1 + a2 * r2 + a3 * r2 * r2)
+        dg = 1.0 - pa * (2.0 * a2 * ra + 4.0 * a3 * r2 * ra)
+        rn = ra - g / dg
+        r[act] = rn
+        act = act[rn != ra]
+        if act.size == 0:
+            break
     r2 = r * r
     conv = np.abs(r - rho * (d1 + d2 * r2 + d3 * r2 * r2)) <= 1e-11 * np.maximum(1.0, r)
     safe = np.where(nxy > 0, nxy, 1.0)
@@ -159,11 +168,13 @@ def _choose_tracks(rng, R, t, d, lm, want):
                 prev = np.empty((0, 2), np.int64)
             key_new = np.stack([jj_local, cc], 1)
             allk = np.concatenate([prev, key_new])
-            pos = np.arange(allk.shape[0])
-            o = np.lexsort((pos, allk[:, 1], allk[:, 0]))
-            ks = allk[o]
+            # pairs ordered by (landmark, camera), draw order among equal
+            # pairs (a stable sort of one combined key)
+            ks = allk[:, 0] * m + allk[:, 1]
+            o = np.argsort(ks, kind="stable")
+            ks = ks[o]
             dup_sorted = np.zeros(ks.shape[0], bool)
-            dup_sorted[1:] = (ks[1:, 0] == ks[:-1, 0]) & (ks[1:, 1] == ks[:-1, 1])
+            dup_sorted[1:] = ks[1:] == ks[:-1]
             dup = np.empty_like(dup_sorted)
             dup[o] = dup_sorted
             dup = dup[prev.shape[0]:]
