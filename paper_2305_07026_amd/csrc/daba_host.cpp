@@ -304,6 +304,7 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.EE = c.take<double>(2 * S);
     p.Fprev = c.take<double>(2 * S);
     p.metrics = c.take<double>(4 * S);
+    p.fsh = c.take<double>(S);
     p.st = c.take<DevState>(2);
     p.trace = c.take<double>(kTraceCap);
     p.trace_cap = kTraceCap;
@@ -687,6 +688,7 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         upload(p.st, st, sizeof st, s);
         std::vector<double> zero(std::max<int64_t>(4 * L.S, 1), 0.0);
         upload(p.metrics, zero.data(), 4 * L.S * sizeof(double), s);
+        upload(p.fsh, zero.data(), L.S * sizeof(double), s);
         std::vector<int> zeroi(L.S, 0);
         upload(p.restart, zeroi.data(), L.S * sizeof(int), s);
         hipcheck(hipStreamSynchronize(s), "sync");
@@ -985,6 +987,13 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
             hipcheck(hipStreamSynchronize(s), "sync");
         }
         write_point(hh, vc.data(), vl.data(), vcp.data(), vlp.data());
+        {
+            // no restart test is stored for the new point: clear the F shares
+            // the next iteration would otherwise sum into an unread trace slot
+            std::vector<double> z(L.S, 0.0);
+            upload(p.fsh, z.data(), L.S * sizeof(double), s);
+            hipcheck(hipStreamSynchronize(s), "sync");
+        }
         if (cc->p4) {
             const int S = L.S;
             const double s2 = p.scale * p.scale;

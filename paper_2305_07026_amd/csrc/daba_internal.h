@@ -117,6 +117,7 @@ struct Params {
     double* EE;               // E^a(x^k | x^(k-1))
     double* Fprev;            // F^a(k-1)
     double* metrics;          // [S*4] of the last iteration
+    double* fsh;              // [S] partition shares of F at the last restart test
     DevState* st;             // [2]
     double* trace;            // [trace_cap]
     int trace_cap;

@@ -273,156 +273,128 @@ __device__ __forceinline__ double next_gamma(const Params& p, double s, double* 
     return p.accelerate ? (s1 - 1.0) / s2 : 0.0;
 }
 
-// Restart test of iteration kp (eq. Fak, lFak, Eak) for every partition, by
-// one block of 256 threads: each wave sums two partitions at a time over the
-// block sums k_entity left (lanes strided, then a wave reduction) and its
-// lane 0 takes the test.  Every caller sums the same values in the same
-// order, so every block that takes the test gets the same answer.  The
-// writer stores the bookkeeping of slot (kp + 1) & 1, the metrics, the flags
-// and the next Nesterov state.  Flags (1: the partition restarts, i.e. keeps
-// the plain MM candidate) and F shares go to s_rs / s_Fsh.  kp may be -1.
-__device__ void part_sums(const Params& p, int a, int lane, double* c, double* l) {
-    const int c0 = p.pcb[a], nc = p.pcb[a + 1] - c0, l0 = p.plb[a], nl = p.plb[a + 1] - l0;
-    const int n = nc > nl ? nc : nl;
-    // unrolled so that several rounds of loads are in flight together
-#pragma unroll 4
-    for (int q = lane; q < n; q += kWave) {
-        if (q < nc) {
-            const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)(c0 + q) * 4);
-            c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
-        }
-        if (q < nl) {
-            const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)(l0 + q) * 2);
-            l[0] += v.x; l[1] += v.y;
+// Restart test of iteration kp (eq. Fak, lFak, Eak), one block per
+// partition a = blockIdx.x.  The block sums the values k_entity left for
+// partition a (its camera blocks' and landmark blocks' sums, threads
+// strided, then a fixed-order block reduction) and thread 0 takes the test.
+// It stores the bookkeeping of slot (kp + 1) & 1, the metrics, the flag
+// (1: the partition restarts, i.e. keeps the plain MM candidate) and the
+// partition's share of F(x^kp).  Block 0 also stores the next Nesterov
+// state and the iteration count.  Every input is requested before the
+// first wait; with skip_if_decided the block returns, before any store,
+// when the test is already stored.  kp may be -1.
+__device__ void restart_test_part(const Params& p, int kp, bool skip_if_decided, double (*red)[6]) {
+    const int a = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int S = p.S;
+    const int cur = (kp & 1) * S;
+    const int decided = skip_if_decided ? p.st[0].decided : 0;
+    double E = 0.0, EE = 0.0, Fbar = 0.0, col0 = 0.0, col1 = 0.0, s_in = 0.0;
+    int64_t k_in = 0;
+    if (tid == 0) {
+        E = p.E[cur + a];
+        EE = p.EE[cur + a];
+        Fbar = p.Fbar[cur + a];
+        col0 = p.colsum[a];
+        col1 = p.colsum[S + a];
+        if (a == 0) {
+            s_in = p.st[kp & 1].s;
+            k_in = p.st[kp & 1].k;
         }
     }
-}
-
-// Per-partition inputs of the test, loaded in the same round as the sums.
-struct TestLds {
-    double E[kMaxPart], EE[kMaxPart], Fbar[kMaxPart], col0[kMaxPart], col1[kMaxPart];
-    double s;
-    int64_t k;
-    int rs[kMaxPart];
-    double Fsh[kMaxPart];
-};
-
-__device__ void test_one(const Params& p, int kp, bool writer, int a, const double* c, const double* l, TestLds& d) {
-    const int S = p.S;
+    double c[4] = {0, 0, 0, 0}, l[2] = {0, 0};
+    {
+        const int c0 = p.pcb[a], nc = p.pcb[a + 1] - c0, l0 = p.plb[a], nl = p.plb[a + 1] - l0;
+        const int n = nc > nl ? nc : nl;
+        // unrolled so that several rounds of loads are in flight together
+#pragma unroll 4
+        for (int q = tid; q < n; q += 256) {
+            if (q < nc) {
+                const double4 v = *reinterpret_cast<const double4*>(p.camblk_vals + (size_t)(c0 + q) * 4);
+                c[0] += v.x; c[1] += v.y; c[2] += v.z; c[3] += v.w;
+            }
+            if (q < nl) {
+                const double2 v = *reinterpret_cast<const double2*>(p.lmblk_vals + (size_t)(l0 + q) * 2);
+                l[0] += v.x; l[1] += v.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = wave_sum(c[q]);
+    l[0] = wave_sum(l[0]);
+    l[1] = wave_sum(l[1]);
+    if (decided) return;  // uniform over the block
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wv][q] = c[q];
+        red[wv][4] = l[0];
+        red[wv][5] = l[1];
+    }
+    __syncthreads();
+    if (tid != 0) return;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double v = 0.0;
+        for (int w = 0; w < 4; ++w) v += red[w][q];
+        if (q < 4) c[q] = v;
+        else l[q - 4] = v;
+    }
     const int nxt = ((kp + 1) & 1) * S;
     // E^a(x^k | x^k): each pair's F split in halves between its sides
-    const double Fsh = c[2] + d.col0[a];
+    const double Fsh = c[2] + col0;
     // [E^a + DeltaE^a](x^k | x^(k-1)) = Fsh + cross-partition gap shares
-    const double V = Fsh + c[3] + d.col1[a];
-    const double Fk = d.E[a] + V - d.EE[a];                        // eq. Fak
-    const double Fb = (1.0 - p.eta) * d.Fbar[a] + p.eta * Fk;      // eq. lFak
+    const double V = Fsh + c[3] + col1;
+    const double Fk = E + V - EE;                        // eq. Fak
+    const double Fb = (1.0 - p.eta) * Fbar + p.eta * Fk;  // eq. lFak
     const double dmm = c[0] + l[0], dacc = c[1] + l[1];
-    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;                  // eq. Eak test
+    int rs = p.accelerate ? (Fk + dacc > Fb) : 1;        // eq. Eak test
     if (p.accelerate && (p.flags & 1)) rs = 0;
     if (p.accelerate && (p.flags & 2)) rs = 1;
     const double dch = rs ? dmm : dacc;
-    d.rs[a] = rs;
-    d.Fsh[a] = Fsh;
-    if (writer) {
-        p.Fprev[nxt + a] = Fk;
-        p.Fbar[nxt + a] = Fb;
-        p.E[nxt + a] = Fk + dch;
-        p.EE[nxt + a] = Fsh + dch;
-        p.metrics[4 * a + 0] = Fk;
-        p.metrics[4 * a + 1] = Fb;
-        p.metrics[4 * a + 2] = Fk + dch;
-        p.metrics[4 * a + 3] = (double)rs;
-        p.restart[a] = rs;
-    }
-}
-
-// With skip_if_decided the block returns (before any store) when the test
-// is already stored; that flag is loaded together with every other input.
-__device__ void restart_test_block(const Params& p, int kp, bool writer, bool skip_if_decided, TestLds& d) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int S = p.S;
-    const int cur = (kp & 1) * S;
-    const int tid = threadIdx.x;
-    const int decided = skip_if_decided ? p.st[0].decided : 0;
-    double in[5] = {0, 0, 0, 0, 0};
-    if (tid < S) {
-        in[0] = p.E[cur + tid];
-        in[1] = p.EE[cur + tid];
-        in[2] = p.Fbar[cur + tid];
-        in[3] = p.colsum[tid];
-        in[4] = p.colsum[S + tid];
-    }
-    double s_in = 0.0;
-    int64_t k_in = 0;
-    if (tid == kWave) {
-        s_in = p.st[kp & 1].s;
-        k_in = p.st[kp & 1].k;
-    }
-    double c0[4] = {0, 0, 0, 0}, l0[2] = {0, 0}, c1[4] = {0, 0, 0, 0}, l1[2] = {0, 0};
-    // the same number of rounds in every wave (the barrier inside is reached
-    // by all of them)
-    const int rounds = (S + 7) / 8;
-    for (int r = 0; r < rounds; ++r) {
-        const int a0 = wv + 8 * r, a1 = a0 + 4;
-        if (a0 < S) part_sums(p, a0, lane, c0, l0);
-        if (a1 < S) part_sums(p, a1, lane, c1, l1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c0[q] = wave_sum(c0[q]);
-            c1[q] = wave_sum(c1[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            l0[q] = wave_sum(l0[q]);
-            l1[q] = wave_sum(l1[q]);
-        }
-        if (r == 0) {
-            if (decided) return;  // uniform over the block
-            if (tid < S) {
-                d.E[tid] = in[0];
-                d.EE[tid] = in[1];
-                d.Fbar[tid] = in[2];
-                d.col0[tid] = in[3];
-                d.col1[tid] = in[4];
-            }
-            if (tid == kWave) {
-                d.s = s_in;
-                d.k = k_in;
-            }
-        }
-        __syncthreads();  // the per-partition inputs are in LDS
-        if (lane == 0) {
-            if (a0 < S) test_one(p, kp, writer, a0, c0, l0, d);
-            if (a1 < S) test_one(p, kp, writer, a1, c1, l1, d);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c0[q] = c1[q] = 0.0;
-        l0[0] = l0[1] = l1[0] = l1[1] = 0.0;
-    }
-    __syncthreads();
-    if (writer && threadIdx.x == 0) {
-        double F = 0.0;
-        for (int a = 0; a < S; ++a) F += d.Fsh[a];
+    p.Fprev[nxt + a] = Fk;
+    p.Fbar[nxt + a] = Fb;
+    p.E[nxt + a] = Fk + dch;
+    p.EE[nxt + a] = Fsh + dch;
+    p.metrics[4 * a + 0] = Fk;
+    p.metrics[4 * a + 1] = Fb;
+    p.metrics[4 * a + 2] = Fk + dch;
+    p.metrics[4 * a + 3] = (double)rs;
+    p.restart[a] = rs;
+    p.fsh[a] = Fsh;
+    if (a == 0) {
         double s1;
-        const double gam = next_gamma(p, d.s, &s1);
-        if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
-        const int64_t kk = d.k;
-        if (kk >= 0) p.trace[kk & (int64_t)(p.trace_cap - 1)] = F;
+        const double gam = next_gamma(p, s_in, &s1);
         DevState& sn = p.st[(kp + 1) & 1];
-        sn.F = F;
         sn.s = s1;
         sn.gamma = gam;
-        sn.k = kk + 1;
+        sn.k = k_in + 1;
     }
 }
 
 // Start of iteration k: the restart test of iteration k - 1, unless it is
 // already stored (after daba_create, daba_set_state or a previous call).
-// One block.
-__global__ __launch_bounds__(256) void k_decide(Params p, int k) {
-    __shared__ TestLds d;
-    restart_test_block(p, k - 1, true, true, d);
+// One block per partition.
+__global__ __launch_bounds__(256) void k_decide(Params p, int k, int skip_if_decided) {
+    __shared__ double red[4][6];
+    restart_test_part(p, k - 1, skip_if_decided != 0, red);
+}
+
+// F(x^(k-1)) from the partition shares the restart test of iteration k - 1
+// stored (summed in partition order), into the trace and the state of slot
+// k & 1; a non-finite F sets the sticky error.  All threads of the block
+// call it.
+__device__ void store_trace(const Params& p, int k, double* sh) {
+    if ((int)threadIdx.x < p.S) sh[threadIdx.x] = p.fsh[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double F = 0.0;
+        for (int a = 0; a < p.S; ++a) F += sh[a];
+        if (!isfinite(F) && p.st[0].err == 0) p.st[0].err = -4;  // a degenerate point reported first wins
+        DevState& sc = p.st[k & 1];
+        const int64_t kk = sc.k - 1;
+        if (kk >= 0) p.trace[kk & (int64_t)(p.trace_cap - 1)] = F;
+        sc.F = F;
+    }
 }
 
 // The restart flags of iteration k - 1 as a bit mask (stored by k_decide).
@@ -1454,6 +1426,7 @@ template <typename RT, bool ACC>
 __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
     __shared__ CamLds sh;
     __shared__ double sred[4][4];  // block reductions
+    __shared__ double fshl[kMaxPart];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     if ((int)blockIdx.x < p.nCamBlocks) {
@@ -1470,6 +1443,8 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
         if (lane == 0) sred[wv][0] = s;
         __syncthreads();
         if (threadIdx.x == 0) p.colsum[cb] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+        // F(x^(k-1)) from the shares this iteration's restart test stored
+        if (cb == 0) store_trace(p, k, fshl);
         return;
     }
     const int lb = cb - 2 * p.S;
@@ -1479,27 +1454,32 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
 
 // ------------------------------------------------------- select and roll
 
-// End of a call, after iteration k - 1: its restart test (every block takes
-// it, block 0 stores it) and the chosen candidates written into both
-// candidate slots and the camera generation k % 3, so that x^k is stored
-// plainly whichever slot is read.
+// End of a call, after the restart test of iteration k - 1 (launched just
+// before): the chosen candidates written into both candidate slots and the
+// camera generation k % 3, so that x^k is stored plainly whichever slot is
+// read; block 0 also stores F(x^(k-1)) in the trace.
 __global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
-    __shared__ TestLds d;
-    restart_test_block(p, k - 1, blockIdx.x == 0, false, d);
-    uint64_t restart = 0;
-    for (int a = 0; a < p.S; ++a) restart |= (uint64_t)(d.rs[a] != 0) << a;
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.st[0].decided = 1;
+    __shared__ double sh[kMaxPart];
+    if (blockIdx.x == 0) {
+        store_trace(p, k, sh);
+        if (threadIdx.x == 0) p.st[0].decided = 1;
+    }
+    const uint64_t restart = restart_mask(p);
     const int par = (k + 1) & 1;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < p.M) {
         const int ci = (int)i;
         const int c = chosen(restart, p.cam_part[ci]);
         const size_t o = (size_t)ci * kCamRec;
+        // per-lane choice between two uniform pointers (indexing the
+        // argument's pointer table per lane would copy it to scratch)
+        const double* xc = c ? p.ccand[par][1] : p.ccand[par][0];
+        const double* xbc = c ? p.cbar[par][1] : p.cbar[par][0];
         double2 x[8], xb[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-            x[a] = reinterpret_cast<const double2*>(p.ccand[par][c] + o)[a];
-            xb[a] = reinterpret_cast<const double2*>(p.cbar[par][c] + o)[a];
+            x[a] = reinterpret_cast<const double2*>(xc + o)[a];
+            xb[a] = reinterpret_cast<const double2*>(xbc + o)[a];
         }
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
@@ -1516,9 +1496,10 @@ __global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
         const int li = (int)j;
         const int c = chosen(restart, p.lm_part[li]);
         const size_t o = (size_t)li * kLmPair;
+        const double* qc = c ? p.lcp[par][1] : p.lcp[par][0];
         double2 q[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) q[a] = reinterpret_cast<const double2*>(p.lcp[par][c] + o)[a];
+        for (int a = 0; a < 4; ++a) q[a] = reinterpret_cast<const double2*>(qc + o)[a];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             reinterpret_cast<double2*>(p.lcp[par][0] + o)[a] = q[a];
@@ -1526,8 +1507,9 @@ __global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
         }
         if (p.fp32) {
             float4 f[2];
+            const float* fc = c ? p.lcp32[par][1] : p.lcp32[par][0];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) f[a] = reinterpret_cast<const float4*>(p.lcp32[par][c] + o)[a];
+            for (int a = 0; a < 2; ++a) f[a] = reinterpret_cast<const float4*>(fc + o)[a];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 reinterpret_cast<float4*>(p.lcp32[par][0] + o)[a] = f[a];
@@ -1838,11 +1820,12 @@ hipError_t launch_entity(const Params& p, int k, hipStream_t s) {
 }
 
 hipError_t launch_decide(const Params& p, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, p, k);
+    hipLaunchKernelGGL(k_decide, dim3(p.S), dim3(256), 0, s, p, k, 1);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Params& p, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(p.S), dim3(256), 0, s, p, k, 0);
     const int64_t n = p.M + p.N;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, k);
     return hipGetLastError();
