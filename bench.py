@@ -45,17 +45,30 @@ def obs_pass_bytes(sol, layout_T: int, fp32: bool, accelerate: bool) -> float:
     return per_obs * sol.K + per_tile * layout_T
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2305_07026_amd", "csrc", "daba_kernels.hip")
+
+
+def source_digest(path: str = KERNEL_SOURCE) -> str:
+    """SHA-256 of a source file's code: comments, trailing blanks and empty
+    lines removed, so that only a change of code changes it."""
+    import hashlib
+    import re
+    t = open(path).read()
+    t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+    t = re.sub(r"//[^\n]*", "", t)
+    t = "\n".join(line.rstrip() for line in t.splitlines() if line.strip())
+    return hashlib.sha256(t.encode()).hexdigest()
+
+
 def measured_traffic(workload: str, precision: str):
     """HBM bytes per launch of the observation pass from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated against a device
-    copy), if they were taken on the kernel source as it is now; else None."""
-    import hashlib
+    copy), if they were taken on the kernel code as it is now; else None."""
     rec = os.path.join(ROOT, "profiles", f"k_obs_traffic_{workload}_{precision}.json")
-    src = os.path.join(ROOT, "paper_2305_07026_amd", "csrc", "daba_kernels.hip")
     if not os.path.exists(rec):
         return None
     t = json.load(open(rec))
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != t["kernel_source_sha256"]:
+    if source_digest() != t.get("kernel_code_sha256"):
         return None
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 

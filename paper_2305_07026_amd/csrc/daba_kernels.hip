@@ -5,10 +5,10 @@
 //
 // Per iteration k (k mod 3 picks the camera generation, k mod 2 the parity
 // of the candidate buffers), three launches:
-//   k_decide   (one block) the restart test of iteration k - 1 (eq. Fak,
-//              lFak, Eak), which picks each partition's candidate (eq.
-//              update_amm or update_mm) as x^k;
-//   k_obs      one wave per camera tile evaluates every observation at x^k,
+//   k_decide   (one block per partition) the restart test of iteration
+//              k - 1 (eq. Fak, lFak, Eak), which picks each partition's
+//              candidate (eq. update_amm or update_mm) as x^k;
+//   k_obs_dma  one wave per camera tile evaluates every observation at x^k,
 //              taken from that candidate, at the extrapolated
 //              x-bar^k and at x^(k-1); accumulates the camera moments of both
 //              surrogates (FP64), the F share and the surrogate-gap share;
@@ -16,12 +16,14 @@
 //              landmark-side record to its slot.
 //   k_entity   camera subproblems (Levenberg-Marquardt on the moments, and
 //              the next extrapolation of each candidate, eq. nesterov_x) and,
-//              in other blocks of the same launch, landmark subproblems (one
-//              lane per landmark: the records k_obs wrote at its slots, then
-//              the closed form) and the column sums of the partition bins.
-// At the end of a call k_finalize takes the last restart test and writes
-// the chosen candidates everywhere, so that between calls x^k is stored
-// plainly.
+//              in other blocks of the same launch, the column sums of the
+//              partition bins (the first also sums the objective the restart
+//              test split by partition) and landmark subproblems (one lane
+//              per landmark: the records k_obs_dma wrote at its slots, then
+//              the closed form).
+// At the end of a call a last k_decide takes the restart test, and
+// k_finalize writes the chosen candidates everywhere, so that between calls
+// x^k is stored plainly.
 //
 // Numerics.  Camera statistics are taken about the linearization point y
 // (Appendix-style moment form): with z = (ux, uy, 1, |u|^2, |u|^4, lambda),
