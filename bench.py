@@ -131,34 +131,38 @@ def cpu_baseline(prob, S, budget_s=15.0, budget_1t_s=6.0):
                 sample_1thread=f"the next {n1} iteration(s) on 1 thread, {dt1:.1f} s wall")
 
 
-def attainable_bandwidth(mib=1024, reps=10):
-    """HBM bandwidth a plain device-to-device copy reaches on this GPU (read
-    + write bytes per second), the practical ceiling next to the vendor
-    peak."""
+def attainable_bandwidth(mib=1024, reps=10, grids=(512, 768, 1024, 1280)):
+    """HBM bandwidth a plain streaming copy reaches on this GPU (read + write
+    bytes per second; the best of a few grid sizes), the practical ceiling
+    next to the vendor peak.  The copy is the library's measurement hook."""
     import torch
-    n = mib * (1 << 20) // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    from paper_2305_07026_amd import binding as B
+    n = mib * (1 << 20)
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    best = 0.0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    for g in grids:
+        for _ in range(2):
+            B.check(B.lib.daba_stream_copy(b.data_ptr(), a.data_ptr(), n, g, sp), "daba_stream_copy")
+        e0.record(stream)
+        for _ in range(reps):
+            B.check(B.lib.daba_stream_copy(b.data_ptr(), a.data_ptr(), n, g, sp), "daba_stream_copy")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = max(best, 2 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9)
     del a, b
     torch.cuda.empty_cache()
-    return gbs
+    return best
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="cam1k-lm200k")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")

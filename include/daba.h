@@ -146,6 +146,14 @@ int daba_get_metrics(daba_handle *h, double *metrics);
  * launch.  Synchronizes. */
 int daba_iterate_timed(daba_handle *h, int n_iters, double *ms_out);
 
+/* Measurement only, not part of the method: enqueues a plain streaming copy
+ * of `bytes` bytes (a multiple of 16; both DEVICE pointers 16-byte aligned,
+ * not overlapping) from src to dst on hip_stream, with `blocks` blocks of
+ * 256 threads, so that a caller can time the bandwidth the GPU attains next
+ * to the kernels of the iteration.  Returns DABA_E_INVAL for a bad argument,
+ * DABA_E_HIP if the launch fails. */
+int daba_stream_copy(void *dst, const void *src, size_t bytes, int blocks, void *hip_stream);
+
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 int daba_destroy(daba_handle *h);
 

@@ -76,10 +76,11 @@ def _load() -> C.CDLL:
     lib.daba_set_state.argtypes = [vp, pd, pd, pd, pd, pd, pd]
     lib.daba_get_metrics.argtypes = [vp, pd]
     lib.daba_destroy.argtypes = [vp]
+    lib.daba_stream_copy.argtypes = [vp, vp, C.c_size_t, i, vp]
     lib.daba_last_error.argtypes = [vp]
     lib.daba_last_error.restype = C.c_char_p
     for name in ("daba_create", "daba_iterate", "daba_iterate_timed", "daba_objective", "daba_grad",
-                 "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy"):
+                 "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy", "daba_stream_copy"):
         getattr(lib, name).restype = C.c_int
     return lib
 
