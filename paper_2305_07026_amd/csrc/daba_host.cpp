@@ -267,10 +267,6 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.group_base = c.take<int64_t>(G);
     p.lmblock_g0 = c.take<int>(L.lmblock_g0.size());
     p.lmblock_g1 = c.take<int>(L.lmblock_g0.size());
-    p.camblock_c0 = c.take<int>(L.camblock_c0.size());
-    p.camblock_c1 = c.take<int>(L.camblock_c0.size());
-    p.part_camblk = c.take<int>(S + 1);
-    p.part_lmblk = c.take<int>(S + 1);
     p.lmblock_part = c.take<int>(L.lmblock_g0.size());
     p.cam_ext = c.take<int>(M);
     p.lm_ext = c.take<int>(N);
@@ -669,10 +665,6 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
         upload((void*)p.group_base, L.group_base.data(), L.G * sizeof(int64_t), s);
         upload((void*)p.lmblock_g0, L.lmblock_g0.data(), L.lmblock_g0.size() * sizeof(int), s);
         upload((void*)p.lmblock_g1, L.lmblock_g1.data(), L.lmblock_g1.size() * sizeof(int), s);
-        upload((void*)p.camblock_c0, L.camblock_c0.data(), L.camblock_c0.size() * sizeof(int), s);
-        upload((void*)p.camblock_c1, L.camblock_c1.data(), L.camblock_c1.size() * sizeof(int), s);
-        upload((void*)p.part_camblk, L.part_camblk.data(), (L.S + 1) * sizeof(int), s);
-        upload((void*)p.part_lmblk, L.part_lmblk.data(), (L.S + 1) * sizeof(int), s);
         upload((void*)p.lmblock_part, L.lmblock_part.data(), L.lmblock_part.size() * sizeof(int), s);
         upload((void*)p.cam_ext, L.cam_ext.data(), L.M * sizeof(int), s);
         upload((void*)p.lm_ext, L.lm_ext.data(), L.N * sizeof(int), s);

@@ -83,12 +83,9 @@ struct Params {
     const int64_t* group_base;
     const int* lmblock_g0;    // [nLmBlocks]
     const int* lmblock_g1;
-    const int* camblock_c0;   // [nCamBlocks]
-    const int* camblock_c1;
-    const int* part_camblk;   // [S+1] camera blocks of each partition
-    const int* part_lmblk;    // [S+1] landmark blocks of each partition
-    // the same two ranges and the first camera of each partition by value
-    // (kernel arguments): a block finds its partition without a memory load
+    // first camera block, landmark block and camera of each partition (so
+    // that a block finds its partition, and the restart test its block
+    // sums, without a memory load)
     int pcb[kMaxPart + 1], plb[kMaxPart + 1], pcam[kMaxPart + 1];
     const int* lmblock_part;  // [nLmBlocks] partition of each landmark block
     const int* cam_ext;       // internal -> caller camera index
