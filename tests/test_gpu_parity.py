@@ -80,6 +80,18 @@ def test_free_running_parity_tiled(tiled):
     assert (np.abs(Fg - Fo) / Fo).max() <= 1e-10
 
 
+@pytest.mark.parametrize("loss", ["trivial", "welsch"])
+def test_free_running_parity_other_losses(tiled, loss):
+    """The other two losses of Assumption 1 (Welsch is non-convex): F after
+    each of 60 iterations within 1e-10 relative, same restart decisions."""
+    g, o = both(tiled, n_partitions=4, loss=loss)
+    Fg = g.iterate(60)
+    Fo, mo = o.iterate(60)
+    r = np.abs(Fg - Fo) / Fo
+    assert r.max() <= 1e-10, (r.argmax(), r.max())
+    assert np.array_equal(g.metrics()[:, 3], mo[-1, :, 3])
+
+
 def test_metrics_and_restart_decisions_each_iteration(c1):
     g, o = both(c1, n_partitions=6, loss="huber", eta=0.7)
     Fo, mo = o.iterate(40)
@@ -118,7 +130,7 @@ def test_one_step_parity_from_common_state(c1):
     assert np.array_equal(g.metrics()[:, 3], mo[0, :, 3])
 
 
-@pytest.mark.parametrize("loss", ["trivial", "huber"])
+@pytest.mark.parametrize("loss", ["trivial", "huber", "welsch"])
 def test_gradient_parity(tiled, loss):
     g, o = both(tiled, loss=loss, n_partitions=2)
     gc, gl, gu = (t.cpu().numpy() for t in g.grad())
@@ -190,6 +202,16 @@ def test_fp32_mixed_within_1e4_after_100(c1):
     r = np.abs(Fg - Fo) / Fo
     assert r[-1] <= 1e-4, r[-1]
     assert r.max() <= 1e-3
+
+
+@pytest.mark.parametrize("loss", ["trivial", "welsch"])
+def test_fp32_mixed_other_losses(c1, loss):
+    g = P.DabaSolver(c1, n_partitions=4, loss=loss, precision="fp32_mixed")
+    o = Oracle(c1, n_partitions=4, loss=loss)
+    Fg = g.iterate(100)
+    Fo, _ = o.iterate(100)
+    r = np.abs(Fg - Fo) / Fo
+    assert r[-1] <= 1e-4, r[-1]
 
 
 def test_edge_cases_empty_entities():
