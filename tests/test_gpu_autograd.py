@@ -114,7 +114,8 @@ def test_fp32_gradient_error(sub):
 
 def test_gradient_parity_differentiation_form():
     """Full differentiation-form size: 1,000 cameras, 200,000 landmarks,
-    ~1.6M observations, against the oracle's gradient."""
+    ~1.6M observations, against the oracle's gradient, in FP64 and in the
+    FP32-mixed form."""
     prob = make_problem("cam1k-lm200k-grad")
     g = P.DabaSolver(prob, loss="huber", n_partitions=8)
     o = Oracle(prob, loss="huber", n_partitions=8)
@@ -125,3 +126,9 @@ def test_gradient_parity_differentiation_form():
     for k in range(12, 15):
         assert np.linalg.norm(gc[:, k] - oc[:, k]) <= 1e-10 * np.linalg.norm(oc[:, k])
     assert abs(g.objective() - o.objective()) <= 1e-12 * o.objective()
+    # the FP32-mixed adjoint at the same size (FP32 residuals: ~1e-4 on e)
+    g32 = P.DabaSolver(prob, loss="huber", n_partitions=8, precision="fp32_mixed")
+    fc, fl, fu = (t.cpu().numpy() for t in g32.grad())
+    for a, b in ((fc, oc), (fl, ol), (fu, ou)):
+        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b)
+    assert abs(g32.objective() - o.objective()) <= 1e-4 * o.objective()
