@@ -173,8 +173,8 @@ def main():
                     help="skip the copy-bandwidth measurement (implied by --copy-calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU path is not "
-              "part of this build).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: every partition runs as a "
+              "camera block of one GPU, and the multi-GPU path is a design, not code.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
