@@ -95,3 +95,14 @@ def test_create_rejects_before_device_work(prob, case):
     assert rc == expect, (rc, B.lib.daba_last_error(None))
     assert not h.value
     assert len(B.lib.daba_last_error(None)) > 0
+
+
+def test_stream_copy_rejects_bad_arguments_before_device_work():
+    # every case fails its argument check before any HIP call
+    a, b = 4096, 8192  # stand-in addresses, never dereferenced
+    assert B.lib.daba_stream_copy(None, b, 64, 16, None) == -1
+    assert B.lib.daba_stream_copy(a, None, 64, 16, None) == -1
+    assert B.lib.daba_stream_copy(a, b, 65, 16, None) == -1  # not a multiple of 16
+    assert B.lib.daba_stream_copy(a + 8, b, 64, 16, None) == -1  # misaligned
+    assert B.lib.daba_stream_copy(a, b, 64, 0, None) == -1
+    assert B.lib.daba_stream_copy(a, b, 0, 16, None) == B.DABA_OK  # nothing to copy
