@@ -45,19 +45,24 @@ def obs_pass_bytes(sol, layout_T: int, fp32: bool, accelerate: bool) -> float:
     return per_obs * sol.K + per_tile * layout_T
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2305_07026_amd", "csrc", "daba_kernels.hip")
+_CSRC = os.path.join(ROOT, "paper_2305_07026_amd", "csrc")
+# the iteration's kernels and the device headers they include
+KERNEL_SOURCES = tuple(os.path.join(_CSRC, f) for f in ("daba_kernels.hip", "daba_internal.h", "daba_rotation.h"))
 
 
-def source_digest(path: str = KERNEL_SOURCE) -> str:
-    """SHA-256 of a source file's code: comments, trailing blanks and empty
-    lines removed, so that only a change of code changes it."""
+def source_digest(paths=KERNEL_SOURCES) -> str:
+    """SHA-256 of the code of the given source files: comments, trailing
+    blanks and empty lines removed, so that only a change of code changes
+    it."""
     import hashlib
     import re
-    t = open(path).read()
-    t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
-    t = re.sub(r"//[^\n]*", "", t)
-    t = "\n".join(line.rstrip() for line in t.splitlines() if line.strip())
-    return hashlib.sha256(t.encode()).hexdigest()
+    h = hashlib.sha256()
+    for path in ([paths] if isinstance(paths, str) else paths):
+        t = open(path).read()
+        t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", "", t)
+        h.update("\n".join(line.rstrip() for line in t.splitlines() if line.strip()).encode())
+    return h.hexdigest()
 
 
 def measured_traffic(workload: str, precision: str):

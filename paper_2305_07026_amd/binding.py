@@ -14,7 +14,8 @@ import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdaba.so")
-HEADER = os.path.join(os.path.dirname(PKG), "include", "daba.h")
+INCLUDE = os.path.join(os.path.dirname(PKG), "include")
+HEADERS = (os.path.join(INCLUDE, "daba.h"), os.path.join(INCLUDE, "daba_part.h"))
 
 DABA_OK = 0
 ERRORS = {-1: "DABA_E_INVAL", -2: "DABA_E_NOMEM", -3: "DABA_E_HIP", -4: "DABA_E_NONFINITE", -5: "DABA_E_DEGENERATE"}
@@ -48,8 +49,8 @@ class DabaError(RuntimeError):
 
 
 def header_symbols() -> list[str]:
-    """Names of the functions include/daba.h declares."""
-    text = open(HEADER).read()
+    """Names of the functions the headers under include/ declare."""
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"\b(daba_[a-z_]+)\s*\(", text)))
 
 
@@ -79,8 +80,20 @@ def _load() -> C.CDLL:
     lib.daba_stream_copy.argtypes = [vp, vp, C.c_size_t, i, vp]
     lib.daba_last_error.argtypes = [vp]
     lib.daba_last_error.restype = C.c_char_p
+    # device-level surrogate (include/daba_part.h)
+    lib.daba_part_workspace_bytes.argtypes = [_P(DabaProblem), _P(DabaOptions)]
+    lib.daba_part_workspace_bytes.restype = C.c_size_t
+    lib.daba_part_create.argtypes = [_P(DabaProblem), _P(DabaOptions), vp, C.c_size_t, vp, _P(vp)]
+    lib.daba_part_iterate.argtypes = [vp, i, pd]
+    lib.daba_part_iterate_timed.argtypes = [vp, i, pd]
+    lib.daba_part_get_state.argtypes = [vp, pd, pd, pd]
+    lib.daba_part_destroy.argtypes = [vp]
+    lib.daba_part_last_error.argtypes = [vp]
+    lib.daba_part_last_error.restype = C.c_char_p
     for name in ("daba_create", "daba_iterate", "daba_iterate_timed", "daba_objective", "daba_grad",
-                 "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy", "daba_stream_copy"):
+                 "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy", "daba_stream_copy",
+                 "daba_part_create", "daba_part_iterate", "daba_part_iterate_timed", "daba_part_get_state",
+                 "daba_part_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -91,4 +104,10 @@ lib = _load()
 def check(rc: int, where: str, handle=None):
     if rc != DABA_OK:
         detail = lib.daba_last_error(handle).decode()
+        raise DabaError(rc, where, detail)
+
+
+def check_part(rc: int, where: str, handle=None):
+    if rc != DABA_OK:
+        detail = lib.daba_part_last_error(handle).decode()
         raise DabaError(rc, where, detail)

@@ -150,6 +150,84 @@ class DabaSolver:
         return m
 
 
+class DabaPartSolver:
+    """One problem on one GPU with the device-level surrogate of eq. Ealpha
+    (include/daba_part.h): pairs inside a partition exact, pairs between
+    partitions majorized, one Levenberg-Marquardt solve per partition.  Same
+    problem dict and options as DabaSolver; FP64 only, inner_steps >= 1."""
+
+    def __init__(self, prob: dict, *, n_partitions=None, camera_partition=None, landmark_partition=None,
+                 unit_scale=512.0, loss="huber", delta=1.0, xi=1e-9, eta=0.5, accelerate=True, inner_steps=1,
+                 debug_flags=0, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("DabaPartSolver needs a GPU (torch.cuda is not available)")
+        self.device = torch.device(device)
+        self.M, self.N, self.K = int(prob["n_cameras"]), int(prob["n_landmarks"]), int(prob["n_obs"])
+        self.S = int(n_partitions if n_partitions is not None else prob.get("n_partitions", 1))
+        self.scale = float(unit_scale)
+        self._keep = dict(
+            cam=_np(prob["obs_camera"], np.int32), lm=_np(prob["obs_landmark"], np.int32),
+            uv=_np(prob["obs_uv"], np.float64), cams=_np(prob["cameras"], np.float64),
+            lms=_np(prob["landmarks"], np.float64),
+            cp=_np(camera_partition, np.int32), lp=_np(landmark_partition, np.int32))
+        k = self._keep
+        self._prob = B.DabaProblem(self.M, self.N, self.K, _ptr(k["cam"], C.c_int32), _ptr(k["lm"], C.c_int32),
+                                   _ptr(k["uv"], C.c_double), _ptr(k["cams"], C.c_double),
+                                   _ptr(k["lms"], C.c_double), self.S, _ptr(k["cp"], C.c_int32),
+                                   _ptr(k["lp"], C.c_int32), self.scale)
+        self._opt = B.DabaOptions(B.LOSS[loss], float(delta), float(xi), float(eta), int(bool(accelerate)),
+                                  int(inner_steps), B.PRECISION["fp64"], int(debug_flags))
+        nbytes = B.lib.daba_part_workspace_bytes(C.byref(self._prob), C.byref(self._opt))
+        if nbytes == 0:
+            h = C.c_void_p()
+            rc = B.lib.daba_part_create(C.byref(self._prob), C.byref(self._opt), None, 0, None, C.byref(h))
+            B.check_part(rc, "daba_part_create")
+        self.workspace_bytes = int(nbytes)
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self._ws.data_ptr() + 255) // 256 * 256
+            self.stream = torch.cuda.current_stream(self.device)
+            h = C.c_void_p()
+            rc = B.lib.daba_part_create(C.byref(self._prob), C.byref(self._opt), C.c_void_p(aligned), nbytes,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        B.check_part(rc, "daba_part_create")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and B is not None and getattr(B, "lib", None) is not None:
+            B.lib.daba_part_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _chk(self, rc, where):
+        B.check_part(rc, where, self._h)
+
+    def iterate(self, n: int, trace: bool = True):
+        """n iterations; returns F after each (pixels^2) when trace is set."""
+        F = np.empty(n) if trace else None
+        self._chk(B.lib.daba_part_iterate(self._h, n, _ptr(F, C.c_double)), "daba_part_iterate")
+        return F
+
+    def iterate_timed(self, n: int) -> dict:
+        """n iterations with every launch group timed; returns ms per group
+        and the LM attempts and Cholesky launches made."""
+        ms = np.zeros(8)
+        self._chk(B.lib.daba_part_iterate_timed(self._h, n, _ptr(ms, C.c_double)), "daba_part_iterate_timed")
+        keys = ("eval", "normal_eq", "schur", "cholesky", "solve", "rest")
+        out = {k: float(v) for k, v in zip(keys, ms[:6])}
+        out.update(lm_attempts=int(ms[6]), cholesky_launches=int(ms[7]))
+        return out
+
+    def get_state(self) -> dict:
+        c, l, m = np.empty((self.M, 15)), np.empty((self.N, 3)), np.empty((self.S, 4))
+        self._chk(B.lib.daba_part_get_state(self._h, _ptr(c, C.c_double), _ptr(l, C.c_double), _ptr(m, C.c_double)),
+                  "daba_part_get_state")
+        return dict(cams=c, lms=l, metrics=m)
+
+
 class DabaObjective(torch.autograd.Function):
     """F(cams, lms, uv) of Problem 1 with the hand-written adjoint of App. D.
 

@@ -106,3 +106,53 @@ def test_stream_copy_rejects_bad_arguments_before_device_work():
     assert B.lib.daba_stream_copy(a + 8, b, 64, 16, None) == -1  # misaligned
     assert B.lib.daba_stream_copy(a, b, 64, 0, None) == -1
     assert B.lib.daba_stream_copy(a, b, 0, 16, None) == B.DABA_OK  # nothing to copy
+
+
+def _part_args(prob, **over):
+    import ctypes as C
+    import numpy as np
+    keep = dict(cam=np.ascontiguousarray(prob["obs_camera"], np.int32),
+                lm=np.ascontiguousarray(prob["obs_landmark"], np.int32),
+                uv=np.ascontiguousarray(prob["obs_uv"], np.float64),
+                cams=np.ascontiguousarray(over.pop("cameras", prob["cameras"]), np.float64),
+                lms=np.ascontiguousarray(over.pop("landmarks", prob["landmarks"]), np.float64))
+    P_ = C.POINTER
+    pr = B.DabaProblem(prob["n_cameras"], prob["n_landmarks"], prob["n_obs"],
+                       keep["cam"].ctypes.data_as(P_(C.c_int32)), keep["lm"].ctypes.data_as(P_(C.c_int32)),
+                       keep["uv"].ctypes.data_as(P_(C.c_double)), keep["cams"].ctypes.data_as(P_(C.c_double)),
+                       keep["lms"].ctypes.data_as(P_(C.c_double)), over.pop("n_partitions", 3), None, None, 512.0)
+    opt = dict(loss=1, loss_delta=1.0, xi=1e-9, eta=0.5, accelerate=1, inner_steps=1, precision=0, debug_flags=0)
+    opt.update(over)
+    return keep, pr, B.DabaOptions(**opt)
+
+
+def test_part_workspace_bytes_on_host(prob):
+    import ctypes as C
+    keep, pr, opt = _part_args(prob)
+    n = B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt))
+    # at least the per-observation Hessian blocks (2 x 27 doubles each)
+    assert n >= 2 * 27 * 8 * prob["n_obs"]
+    for bad in (dict(precision=1), dict(inner_steps=0), dict(xi=0.0), dict(n_partitions=65)):
+        keep, pr, opt = _part_args(prob, **bad)
+        assert B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt)) == 0, bad
+
+
+@pytest.mark.parametrize("case", ["fp32", "inner0", "eta", "not_rotation", "degenerate", "null_ws"])
+def test_part_create_rejects_before_device_work(prob, case):
+    import ctypes as C
+    import numpy as np
+    over = {"fp32": dict(precision=1), "inner0": dict(inner_steps=0), "eta": dict(eta=1.5), "null_ws": {}}.get(case, {})
+    if case == "not_rotation":
+        c = prob["cameras"].copy()
+        c[0, :9] *= 2.0
+        over = dict(cameras=c)
+    if case == "degenerate":
+        lms = prob["landmarks"].copy()
+        lms[prob["obs_landmark"][0]] = prob["cameras"][prob["obs_camera"][0], 9:12]
+        over = dict(landmarks=lms)
+    keep, pr, opt = _part_args(prob, **over)
+    h = C.c_void_p()
+    rc = B.lib.daba_part_create(C.byref(pr), C.byref(opt), None, 0, None, C.byref(h))
+    assert rc == (-5 if case == "degenerate" else -1), (case, rc, B.lib.daba_part_last_error(None))
+    assert not h.value
+    assert B.lib.daba_part_last_error(None)

@@ -1,0 +1,120 @@
+"""GPU path of the device-level surrogate (include/daba_part.h) against the
+partition-level oracle (oracle/partition.py), element by element on the same
+seeded inputs, through the C ABI.
+
+Tolerances.  Both sides compute in FP64; they differ in summation order and in
+how each LM system is solved (the oracle: one dense Cholesky of the whole
+partition system; the GPU: landmark elimination and a blocked Cholesky of the
+reduced camera system).  A solve of a system with condition number kappa
+agrees to about kappa * 1e-16; with the damping and kappa <= 1e4 here that is
+1e-12 per step.  Every accept/reject decision is taken on a strict decrease of
+E^a and matches unless two values tie to that level.  The objective after each
+iteration is checked at 1e-9 relative, the final state at 1e-6 (the flat
+intrinsic directions d2, d3 amplify step differences), the per-partition
+metrics at 1e-8.
+"""
+
+import numpy as np
+import pytest
+
+from oracle.partition import PartOracle
+from synth import make_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+P = pytest.importorskip("paper_2305_07026_amd")
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def nrel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def small():
+    # 24 cameras, 600 landmarks, ~4,800 observations: at S = 1 the reduced
+    # system has order 216 (four 64-tiles, the last one ragged)
+    return make_problem("cam50-lm5k", n_cameras=24, n_landmarks=600, seed=41)
+
+
+@pytest.fixture(scope="module")
+def geom():
+    # geometric track lengths, cameras with many observations
+    return make_problem("cam50-lm5k", n_cameras=15, n_landmarks=900, track="geom6", seed=43)
+
+
+def run_both(prob, n, **kw):
+    print(f"partition parity: M={prob['n_cameras']} N={prob['n_landmarks']} K={prob['n_obs']} {kw}", flush=True)
+    g = P.DabaPartSolver(prob, **kw)
+    names = {"camera_partition": "cam_part", "landmark_partition": "lm_part", "debug_flags": "flags"}
+    o = PartOracle(prob, **{names.get(k, k): v for k, v in kw.items()})
+    Fg = g.iterate(n)
+    Fo, mo = o.iterate(n)
+    st = g.get_state()
+    c_o, l_o = o.get_state()
+    print(f"  F rel {rel(Fg, Fo):.2e}  cams {nrel(st['cams'][:, :12], c_o[:, :12]):.2e}  "
+          f"lms {nrel(st['lms'], l_o):.2e}  metrics {rel(st['metrics'][:, :3], mo[-1, :, :3]):.2e}", flush=True)
+    return g, o, Fg, Fo, st, mo
+
+
+@pytest.mark.parametrize("S,loss,acc", [(1, "trivial", False), (3, "huber", True), (4, "welsch", True),
+                                        (2, "huber", False)])
+def test_iterations_match_the_oracle(small, S, loss, acc):
+    g, o, Fg, Fo, st, mo = run_both(small, 8, n_partitions=S, loss=loss, accelerate=acc)
+    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
+    c_o, l_o = o.get_state()
+    assert nrel(st["lms"], l_o) <= 1e-6
+    assert nrel(st["cams"][:, :12], c_o[:, :12]) <= 1e-6
+    np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
+    assert rel(st["metrics"][:, :3], mo[-1, :, :3]) <= 1e-8
+    g.close()
+
+
+def test_custom_partitions_and_a_device_without_cameras(geom):
+    """Cameras scattered over two devices by a seeded draw; a third device
+    holds only landmarks (every pair it touches is split)."""
+    rng = np.random.default_rng(5)
+    M, N = geom["n_cameras"], geom["n_landmarks"]
+    cp = rng.integers(0, 2, M).astype(np.int32)
+    lp = rng.integers(0, 3, N).astype(np.int32)
+    g, o, Fg, Fo, st, mo = run_both(geom, 6, n_partitions=3, camera_partition=cp, landmark_partition=lp,
+                                    loss="huber", accelerate=True)
+    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
+    np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
+
+
+def test_inner_steps_and_restart_flags(small):
+    g, o, Fg, Fo, st, mo = run_both(small, 5, n_partitions=3, loss="huber", inner_steps=3)
+    assert rel(Fg, Fo) <= 1e-9
+    for flags in (1, 2):
+        g, o, Fg, Fo, st, mo = run_both(small, 4, n_partitions=3, loss="huber", debug_flags=flags)
+        assert rel(Fg, Fo) <= 1e-9
+        np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
+
+
+def test_bitwise_reproducible(small):
+    a = P.DabaPartSolver(small, n_partitions=3, loss="huber")
+    b = P.DabaPartSolver(small, n_partitions=3, loss="huber")
+    Fa, Fb = a.iterate(5), b.iterate(5)
+    np.testing.assert_array_equal(Fa, Fb)
+    np.testing.assert_array_equal(a.get_state()["cams"], b.get_state()["cams"])
+
+
+def test_no_observations():
+    prob = make_problem("cam50-lm5k", n_cameras=6, n_landmarks=40, seed=3)
+    empty = dict(prob, n_obs=0, obs_camera=prob["obs_camera"][:0], obs_landmark=prob["obs_landmark"][:0],
+                 obs_uv=prob["obs_uv"][:0])
+    g = P.DabaPartSolver(empty, n_partitions=2, loss="huber")
+    F = g.iterate(3)
+    np.testing.assert_array_equal(F, 0.0)
+    st = g.get_state()
+    np.testing.assert_allclose(st["cams"], prob["cameras"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st["lms"], prob["landmarks"], rtol=0, atol=1e-12)
