@@ -71,6 +71,9 @@ struct PP {
     const double* ouv;
     const int *cam_off, *lm_off, *lm_obs;
     const int *seg_off, *ent;
+    const int4* chunk;                 // reduction chunks: (kind, partition, begin, end)
+    int chunk_base[kMaxS + 1];         // chunks of each partition
+    double* partial;                   // one sum per chunk
     double *vc, *vl, *Hcl, *T;
     double *Hcc, *gc, *W, *Wg;
     double *Smat, *vec;
@@ -314,35 +317,57 @@ __global__ __launch_bounds__(256) void kp_eval(PP p, const double* xc, const dou
     p.vl[o] = vl;
 }
 
-// Block a: the partition's sum of the shares (camera-side shares over its
-// cameras' observations, landmark-side over its landmarks'), plus
-// +-xi/2 |x^a - y^a|^2 for EV_E / EV_GAP, into ps[a][slot].  Fixed order.
-__global__ __launch_bounds__(256) void kp_reduce(PP p, const double* xc, const double* xl, const double* yc,
-                                                 const double* yl, int mode, int slot) {
+// Partition sums of the shares, in two fixed-order levels.  A chunk is one
+// of: camera-side shares of a run of the partition's observations (its
+// cameras' observations are contiguous), landmark-side shares of a run of its
+// landmarks' observations, or the proximal term of a run of its cameras or
+// landmarks (+xi/2 |x - y|^2 for EV_E, -xi/2 for EV_GAP, none for EV_F).
+enum { CH_CAM_OBS = 0, CH_LM_OBS = 1, CH_CAM_PROX = 2, CH_LM_PROX = 3 };
+constexpr int kChunk = 2048;     // observations or landmarks per chunk
+constexpr int kChunkCam = 256;   // cameras per proximal chunk
+
+__global__ __launch_bounds__(256) void kp_reduce1(PP p, const double* xc, const double* xl, const double* yc,
+                                                  const double* yl, int mode) {
     __shared__ double red[4];
-    const int a = blockIdx.x;
+    const int4 ch = p.chunk[blockIdx.x];
     const int tid = threadIdx.x;
     double s = 0.0;
-    for (int o = p.cam_off[p.pc[a]] + tid; o < p.cam_off[p.pc[a + 1]]; o += 256) s += p.vc[o];
-    for (int q = p.lm_off[p.pl[a]] + tid; q < p.lm_off[p.pl[a + 1]]; q += 256) s += p.vl[p.lm_obs[q]];
-    if (mode != EV_F) {
+    if (ch.x == CH_CAM_OBS) {
+#pragma unroll 8
+        for (int o = ch.z + tid; o < ch.w; o += 256) s += p.vc[o];
+    } else if (ch.x == CH_LM_OBS) {
+#pragma unroll 8
+        for (int q = ch.z + tid; q < ch.w; q += 256) s += p.vl[p.lm_obs[q]];
+    } else if (mode != EV_F) {
         double pr = 0.0;
-        for (int i = p.pc[a] + tid; i < p.pc[a + 1]; i += 256)
-            for (int k = 0; k < 15; ++k) {
-                const double d = xc[(size_t)i * kCS + k] - yc[(size_t)i * kCS + k];
-                pr += d * d;
-            }
-        for (int j = p.pl[a] + tid; j < p.pl[a + 1]; j += 256)
-            for (int k = 0; k < 3; ++k) {
-                const double d = xl[(size_t)j * kLS + k] - yl[(size_t)j * kLS + k];
-                pr += d * d;
-            }
-        s += (mode == EV_E ? 0.5 : -0.5) * p.xi * pr;
+        if (ch.x == CH_CAM_PROX) {
+            for (int i = ch.z + tid; i < ch.w; i += 256)
+                for (int k = 0; k < 15; ++k) {
+                    const double d = xc[(size_t)i * kCS + k] - yc[(size_t)i * kCS + k];
+                    pr += d * d;
+                }
+        } else {
+            for (int j = ch.z + tid; j < ch.w; j += 256)
+                for (int k = 0; k < 3; ++k) {
+                    const double d = xl[(size_t)j * kLS + k] - yl[(size_t)j * kLS + k];
+                    pr += d * d;
+                }
+        }
+        s = (mode == EV_E ? 0.5 : -0.5) * p.xi * pr;
     }
     s = wsum(s);
     if ((tid & 63) == 0) red[tid >> 6] = s;
     __syncthreads();
-    if (tid == 0) p.ps[(size_t)a * kPS + slot] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (tid == 0) p.partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One wave per partition: the sum of its chunks into ps[a][slot].
+__global__ __launch_bounds__(64) void kp_reduce2(PP p, int slot) {
+    const int a = blockIdx.x, lane = threadIdx.x;
+    double s = 0.0;
+    for (int c = p.chunk_base[a] + lane; c < p.chunk_base[a + 1]; c += kW) s += p.partial[c];
+    s = wsum(s);
+    if (lane == 0) p.ps[(size_t)a * kPS + slot] = s;
 }
 
 // eq. Fak and eq. lFak from the gap in P_RED
@@ -634,7 +659,9 @@ __global__ __launch_bounds__(64) void kp_rhs(PP p) {
 // One wave per lower 9x9 block (q1 >= q2) of a partition's reduced camera
 // system: S = [q1 == q2] (H_cc + mu diag H_cc) - sum over the block's pairs of
 // T(o1) H_cl(o2)^T, the pairs (two exact observations of one landmark by
-// cameras q1 and q2) in the fixed order of the pair list.
+// cameras q1 and q2) taken from the pair list.  Lane = (pair slot, row third
+// g = lane & 3, slot 3 idle): 16 pairs at a time, each lane a 3x9 piece; a
+// butterfly over the slots then sums the pieces in a fixed order.
 __global__ __launch_bounds__(256) void kp_schur(PP p) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gb = blockIdx.x * 4 + wv;
@@ -650,87 +677,130 @@ __global__ __launch_bounds__(256) void kp_schur(PP p) {
     const int i1 = p.pc[a] + q1;
     const double mu = q[P_MU];
     const int e0 = p.seg_off[gb], e1 = p.seg_off[gb + 1];
-    const int np = p.npad[a];
-    double* Sa = p.Smat + p.soff[a];
-    for (int e = lane; e < 81; e += kW) {
-        const int r = e / 9, c = e % 9;
-        double s = 0.0;
-        for (int k = e0; k < e1; ++k) {
-            const double* t = p.T + (size_t)p.ent[2 * k] * 27 + 3 * r;
-            const double* h = p.Hcl + (size_t)p.ent[2 * k + 1] * 27 + 3 * c;
-            s += t[0] * h[0] + t[1] * h[1] + t[2] * h[2];
+    const int g = lane & 3, slot = lane >> 2;
+    double acc[3][9];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 9; ++v) acc[u][v] = 0.0;
+    if (g < 3) {
+        for (int e = e0 + slot; e < e1; e += 16) {
+            const double* t = p.T + (size_t)p.ent[2 * e] * 27 + 9 * g;  // rows 3g .. 3g+2 of T(o1)
+            const double* h = p.Hcl + (size_t)p.ent[2 * e + 1] * 27;    // H_cl(o2), 9 x 3
+            double tv[9], hv[27];
+#pragma unroll
+            for (int x = 0; x < 9; ++x) tv[x] = t[x];
+#pragma unroll
+            for (int x = 0; x < 27; ++x) hv[x] = h[x];
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    acc[u][v] += tv[3 * u] * hv[3 * v] + tv[3 * u + 1] * hv[3 * v + 1] + tv[3 * u + 2] * hv[3 * v + 2];
         }
-        double v = -s;
-        if (q1 == q2) {
-            const double hc = p.Hcc[(size_t)i1 * 81 + e];
-            v += (r == c) ? hc * (1.0 + mu) : hc;
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            double x = acc[u][v];
+            for (int off = 4; off < kW; off <<= 1) x += __shfl_xor(x, off, kW);
+            acc[u][v] = x;
         }
-        Sa[(size_t)(9 * q1 + r) * np + 9 * q2 + c] = v;
+    if (lane < 3) {  // lane g now holds rows 3g .. 3g+2 summed over every pair
+        const int np = p.npad[a];
+        double* Sa = p.Smat + p.soff[a];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                const int r = 3 * g + u;
+                double val = -acc[u][v];
+                if (q1 == q2) {
+                    const double hc = p.Hcc[(size_t)i1 * 81 + 9 * r + v];
+                    val += (r == v) ? hc * (1.0 + mu) : hc;
+                }
+                Sa[(size_t)(9 * q1 + r) * np + 9 * q2 + v] = val;
+            }
     }
 }
 
-// Blocked right-looking Cholesky, step k: factor the diagonal tile in LDS.
-__global__ __launch_bounds__(256) void kp_chol_diag(PP p, int k) {
-    __shared__ double A[kNB][kNB + 1];
+// Lane j's value of x (j uniform): two v_readlane, no LDS round trip.
+__device__ __forceinline__ double lane_value(double x, int j) {
+    const int2 v = __builtin_bit_cast(int2, x);
+    int2 o;
+    o.x = __builtin_amdgcn_readlane(v.x, j);
+    o.y = __builtin_amdgcn_readlane(v.y, j);
+    return __builtin_bit_cast(double, o);
+}
+
+// Blocked right-looking Cholesky, step k: factor the diagonal tile with one
+// wave, lane r holding row r in registers (column c: L_cc = sqrt(A_cc), the
+// rows below scale, then A_rj -= L_rc L_jc with L_jc broadcast from lane j).
+// The 64 loads of a row are issued together.
+__global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
     const int a = blockIdx.x;
     double* q = p.ps + (size_t)a * kPS;
     if (q[P_ACTIVE] == 0.0 || k >= p.nt[a]) return;
     const int np = p.npad[a];
-    double* Sa = p.Smat + p.soff[a] + (size_t)(kNB * k) * np + kNB * k;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kNB * kNB; e += 256) {
-        const int r = e / kNB, c = e % kNB;
-        A[r][c] = r >= c ? Sa[(size_t)r * np + c] : 0.0;
-    }
-    __syncthreads();
+    double* Sr = p.Smat + p.soff[a] + (size_t)(kNB * k + threadIdx.x) * np + kNB * k;
+    const int r = threadIdx.x;
+    double row[kNB];
+#pragma unroll
+    for (int m = 0; m < kNB; ++m) row[m] = Sr[m];
+#pragma unroll
+    for (int m = 0; m < kNB; ++m) row[m] = m <= r ? row[m] : 0.0;
     bool bad = false;
+#pragma unroll
     for (int c = 0; c < kNB; ++c) {
-        const double d = A[c][c];
-        const double l = d > 0.0 ? sqrt(d) : 1.0;
+        const double d = lane_value(row[c], c);
         bad = bad || !(d > 0.0);
-        __syncthreads();
-        if (tid > c && tid < kNB) A[tid][c] /= l;
-        if (tid == 0) A[c][c] = l;
-        __syncthreads();
-        for (int e = tid; e < kNB * kNB; e += 256) {
-            const int r = e / kNB, cc = e % kNB;
-            if (cc > c && r >= cc) A[r][cc] -= A[r][c] * A[cc][c];
+        const double l = d > 0.0 ? sqrt(d) : 1.0;
+        row[c] = r > c ? row[c] / l : (r == c ? l : row[c]);
+#pragma unroll
+        for (int j = c + 1; j < kNB; ++j) {
+            const double ljc = lane_value(row[c], j);
+            row[j] = r >= j ? row[j] - row[c] * ljc : row[j];
         }
-        __syncthreads();
     }
-    if (tid == 0 && bad) q[P_OK] = 0.0;
-    for (int e = tid; e < kNB * kNB; e += 256) {
-        const int r = e / kNB, c = e % kNB;
-        if (r >= c) Sa[(size_t)r * np + c] = A[r][c];
-    }
+    if (r == 0 && bad) q[P_OK] = 0.0;
+#pragma unroll
+    for (int m = 0; m < kNB; ++m)
+        if (m <= r) Sr[m] = row[m];
 }
 
-// Step k: L_ik = A_ik L_kk^-T for every tile row i > k.  One lane per row of
-// the tile; the rows are kept transposed in LDS (Xt[col][row]) so that the
-// lanes read consecutive words.  64 KB of LDS.
+// Step k: L_ik = A_ik L_kk^-T for every tile row i > k.  Lane r solves row r
+// of the tile, x L_kk^T = a, by forward substitution in registers; L_kk is
+// staged in LDS and read by broadcast.
 __global__ __launch_bounds__(64) void kp_chol_trsm(PP p, int k) {
-    __shared__ double L[kNB][kNB];
-    __shared__ double Xt[kNB][kNB];
+    __shared__ double L[kNB][kNB + 1];
     const int a = blockIdx.y;
     const int i = k + 1 + blockIdx.x;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0 || i >= p.nt[a]) return;
     const int np = p.npad[a];
     const double* Lkk = p.Smat + p.soff[a] + (size_t)(kNB * k) * np + kNB * k;
-    double* Aik = p.Smat + p.soff[a] + (size_t)(kNB * i) * np + kNB * k;
-    const int tid = threadIdx.x;
-    for (int r = 0; r < kNB; ++r) {
-        L[r][tid] = tid <= r ? Lkk[(size_t)r * np + tid] : 0.0;
-        Xt[tid][r] = Aik[(size_t)r * np + tid];
+    double* Ar = p.Smat + p.soff[a] + (size_t)(kNB * i + threadIdx.x) * np + kNB * k;
+    const int t = threadIdx.x;
+    double x[kNB];
+#pragma unroll
+    for (int m = 0; m < kNB; ++m) x[m] = Ar[m];
+    {
+        double col[kNB];
+#pragma unroll
+        for (int rr = 0; rr < kNB; ++rr) col[rr] = Lkk[(size_t)rr * np + t];
+#pragma unroll
+        for (int rr = 0; rr < kNB; ++rr) L[rr][t] = col[rr];
     }
     __syncthreads();
-    // row tid of X solves x L^T = a: x_c = (a_c - sum_{m < c} x_m L_cm) / L_cc
+#pragma unroll
     for (int c = 0; c < kNB; ++c) {
-        double s = Xt[c][tid];
-        for (int m = 0; m < c; ++m) s -= Xt[m][tid] * L[c][m];
-        Xt[c][tid] = s / L[c][c];
+        double s = x[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) s -= x[m] * L[c][m];
+        x[c] = s / L[c][c];
     }
-    __syncthreads();
-    for (int r = 0; r < kNB; ++r) Aik[(size_t)r * np + tid] = Xt[tid][r];
+#pragma unroll
+    for (int m = 0; m < kNB; ++m) Ar[m] = x[m];
 }
 
 // Step k: A_ij -= L_ik L_jk^T for tiles k < j <= i; the inner dimension in
@@ -760,10 +830,18 @@ __global__ __launch_bounds__(256) void kp_chol_update(PP p, int k) {
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     for (int h = 0; h < kNB; h += kH) {
         __syncthreads();
-        for (int e = tid; e < kNB * kH; e += 256) {
-            const int r = e / kH, c = e % kH;
-            Li[r][c] = base[(size_t)(kNB * i + r) * np + kNB * k + h + c];
-            Lj[r][c] = base[(size_t)(kNB * j + r) * np + kNB * k + h + c];
+        double vi[kNB * kH / 256], vj[kNB * kH / 256];
+#pragma unroll
+        for (int u = 0; u < kNB * kH / 256; ++u) {
+            const int e = tid + 256 * u, r = e / kH, c = e % kH;
+            vi[u] = base[(size_t)(kNB * i + r) * np + kNB * k + h + c];
+            vj[u] = base[(size_t)(kNB * j + r) * np + kNB * k + h + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kNB * kH / 256; ++u) {
+            const int e = tid + 256 * u, r = e / kH, c = e % kH;
+            Li[r][c] = vi[u];
+            Lj[r][c] = vj[u];
         }
         __syncthreads();
         for (int kk = 0; kk < kH; ++kk) {
@@ -785,11 +863,14 @@ __global__ __launch_bounds__(256) void kp_chol_update(PP p, int k) {
         for (int v = 0; v < 4; ++v) Aij[(size_t)(r0 + u) * np + c0 + v] -= acc[u][v];
 }
 
-// L L^T x = b in place on the partition's vector: forward then backward
-// substitution, one 64-row tile at a time.
+// L L^T x = b in place on the partition's vector, one 64-row tile at a time:
+// solve the tile's triangle in registers (one wave, lane = row), then take
+// the solved values out of the rest of the right-hand side (forward: one lane
+// per row below the tile, reading its 64 entries; backward: one lane per row
+// above the tile, reading the tile's rows of L, consecutive across lanes).
 __global__ __launch_bounds__(256) void kp_trsv(PP p) {
     __shared__ double xs[kNB];
-    __shared__ double part[4][kNB];
+    __shared__ double D[kNB][kNB + 1];  // the current diagonal tile
     const int a = blockIdx.x;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0) return;
     const int np = p.npad[a], nt = p.nt[a];
@@ -799,48 +880,92 @@ __global__ __launch_bounds__(256) void kp_trsv(PP p) {
     for (int kt = 0; kt < nt; ++kt) {
         const int c0 = kNB * kt;
         if (tid < kNB) xs[tid] = b[c0 + tid];
+        {
+            double v[kNB * kNB / 256];
+#pragma unroll
+            for (int u = 0; u < kNB * kNB / 256; ++u) {
+                const int e = tid + 256 * u;
+                v[u] = L[(size_t)(c0 + e / kNB) * np + c0 + e % kNB];
+            }
+#pragma unroll
+            for (int u = 0; u < kNB * kNB / 256; ++u) {
+                const int e = tid + 256 * u;
+                D[e / kNB][e % kNB] = v[u];
+            }
+        }
         __syncthreads();
         if (tid < kNB) {  // wave 0, lane = row of the tile: forward sweep in registers
             double xv = xs[tid];
+            double drow[kNB];
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) drow[c] = D[tid][c];
+#pragma unroll
             for (int c = 0; c < kNB; ++c) {
-                const double xc = __shfl(xv, c, kW) / L[(size_t)(c0 + c) * np + c0 + c];
-                if (tid == c) xv = xc;
-                if (tid > c) xv -= L[(size_t)(c0 + tid) * np + c0 + c] * xc;
+                const double xc = lane_value(xv, c) / lane_value(drow[c], c);
+                xv = tid == c ? xc : (tid > c ? xv - drow[c] * xc : xv);
             }
             xs[tid] = xv;
+            b[c0 + tid] = xv;
         }
         __syncthreads();
-        if (tid < kNB) b[c0 + tid] = xs[tid];
         for (int r = c0 + kNB + tid; r < np; r += 256) {
-            double s = 0.0;
-            for (int c = 0; c < kNB; ++c) s += L[(size_t)r * np + c0 + c] * xs[c];
-            b[r] -= s;
+            const double* Lr = L + (size_t)r * np + c0;
+            double v[kNB];
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) v[c] = Lr[c];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < kNB; c += 2) {
+                s0 += v[c] * xs[c];
+                s1 += v[c + 1] * xs[c + 1];
+            }
+            b[r] -= s0 + s1;
         }
         __syncthreads();
     }
     for (int kt = nt - 1; kt >= 0; --kt) {
         const int c0 = kNB * kt;
-        // b_c -= sum over rows below the tile of L_rc x_r
+        if (tid < kNB) xs[tid] = b[c0 + tid];
         {
-            const int c = tid & 63, w = tid >> 6;
-            double s = 0.0;
-            for (int r = c0 + kNB + w; r < np; r += 4) s += L[(size_t)r * np + c0 + c] * b[r];
-            part[w][c] = s;
+            double v[kNB * kNB / 256];
+#pragma unroll
+            for (int u = 0; u < kNB * kNB / 256; ++u) {
+                const int e = tid + 256 * u;
+                v[u] = L[(size_t)(c0 + e / kNB) * np + c0 + e % kNB];
+            }
+#pragma unroll
+            for (int u = 0; u < kNB * kNB / 256; ++u) {
+                const int e = tid + 256 * u;
+                D[e / kNB][e % kNB] = v[u];
+            }
         }
-        __syncthreads();
-        if (tid < kNB) xs[tid] = b[c0 + tid] - ((part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]));
         __syncthreads();
         if (tid < kNB) {  // backward sweep with L^T: (L^T)_(tid, c) = L_(c, tid)
             double xv = xs[tid];
+            double dcol[kNB];
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) dcol[c] = D[c][tid];
+#pragma unroll
             for (int c = kNB - 1; c >= 0; --c) {
-                const double xc = __shfl(xv, c, kW) / L[(size_t)(c0 + c) * np + c0 + c];
-                if (tid == c) xv = xc;
-                if (tid < c) xv -= L[(size_t)(c0 + c) * np + c0 + tid] * xc;
+                const double xc = lane_value(xv, c) / lane_value(dcol[c], c);
+                xv = tid == c ? xc : (tid < c ? xv - dcol[c] * xc : xv);
             }
             xs[tid] = xv;
+            b[c0 + tid] = xv;
         }
         __syncthreads();
-        if (tid < kNB) b[c0 + tid] = xs[tid];
+        for (int r = tid; r < c0; r += 256) {
+            double v[kNB];
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) v[c] = L[(size_t)(c0 + c) * np + r];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < kNB; c += 2) {
+                s0 += v[c] * xs[c];
+                s1 += v[c + 1] * xs[c + 1];
+            }
+            b[r] -= s0 + s1;
+        }
         __syncthreads();
     }
 }
@@ -1025,6 +1150,7 @@ struct PLayout {
     std::vector<int> nt, npad, voff, blkbase;
     std::vector<int64_t> soff;
     std::vector<int> seg_off, ent;
+    std::vector<int> chunk, chunk_base;  // 4 ints per chunk; [S+1]
     int64_t smat_total = 0;
     int vec_total = 0;
 };
@@ -1203,6 +1329,25 @@ void build_layout(const daba_problem* pr, PLayout& L) {
     }
     L.seg_off.resize(TB + 1);
     for (int b = 0; b <= TB; ++b) L.seg_off[b] = (int)cnt[b];
+    // reduction chunks, partition by partition
+    L.chunk.clear();
+    L.chunk_base.assign(S + 1, 0);
+    auto add = [&](int kind, int a, int lo, int hi, int step) {
+        for (int x = lo; x < hi; x += step) {
+            L.chunk.push_back(kind);
+            L.chunk.push_back(a);
+            L.chunk.push_back(x);
+            L.chunk.push_back(std::min(hi, x + step));
+        }
+    };
+    for (int a = 0; a < S; ++a) {
+        L.chunk_base[a] = (int)(L.chunk.size() / 4);
+        add(CH_CAM_OBS, a, L.cam_off[L.pc[a]], L.cam_off[L.pc[a + 1]], kChunk);
+        add(CH_LM_OBS, a, L.lm_off[L.pl[a]], L.lm_off[L.pl[a + 1]], kChunk);
+        add(CH_CAM_PROX, a, L.pc[a], L.pc[a + 1], kChunkCam);
+        add(CH_LM_PROX, a, L.pl[a], L.pl[a + 1], kChunk);
+    }
+    L.chunk_base[S] = (int)(L.chunk.size() / 4);
 }
 
 struct Carve {
@@ -1237,6 +1382,8 @@ void carve(const PLayout& L, Carve& c, PP& p, Bufs& b) {
     p.lm_obs = c.take<int>(K);
     p.seg_off = c.take<int>(L.seg_off.size());
     p.ent = c.take<int>(L.ent.size());
+    p.chunk = c.take<int4>(L.chunk.size() / 4);
+    p.partial = c.take<double>(L.chunk.size() / 4);
     p.vc = c.take<double>(K);
     p.vl = c.take<double>(K);
     p.Hcl = c.take<double>(27 * K);
@@ -1299,7 +1446,9 @@ void eval_reduce_t(daba_part_handle* h, const double* xc, const double* xl, cons
                    int mode, int slot) {
     const PP& p = h->p;
     if (p.K > 0) hipLaunchKernelGGL(kp_eval<LOSS>, dim3(gdim(p.K, 256)), dim3(256), 0, h->stream, p, xc, xl, yc, yl, mode);
-    hipLaunchKernelGGL(kp_reduce, dim3(p.S), dim3(256), 0, h->stream, p, xc, xl, yc, yl, mode, slot);
+    const int nch = p.chunk_base[p.S];
+    if (nch > 0) hipLaunchKernelGGL(kp_reduce1, dim3(nch), dim3(256), 0, h->stream, p, xc, xl, yc, yl, mode);
+    hipLaunchKernelGGL(kp_reduce2, dim3(p.S), dim3(64), 0, h->stream, p, slot);
 }
 
 void eval_reduce(daba_part_handle* h, const double* xc, const double* xl, const double* yc, const double* yl,
@@ -1356,7 +1505,7 @@ void lm_all(daba_part_handle* h, const double* yc, const double* yl, double* oc,
         {
             Timed t(h, C_CHOL);
             for (int k = 0; k < ntmax; ++k) {
-                hipLaunchKernelGGL(kp_chol_diag, dim3(p.S), dim3(256), 0, h->stream, p, k);
+                hipLaunchKernelGGL(kp_chol_diag, dim3(p.S), dim3(64), 0, h->stream, p, k);
                 const int m = ntmax - k - 1;
                 if (m > 0) {
                     hipLaunchKernelGGL(kp_chol_trsm, dim3(m, p.S), dim3(64), 0, h->stream, p, k);
@@ -1535,6 +1684,8 @@ int daba_part_create(const daba_problem* prob, const daba_options* opt, void* de
         up((void*)p.lm_obs, L.lm_obs.data(), 4 * K);
         up((void*)p.seg_off, L.seg_off.data(), 4 * L.seg_off.size());
         up((void*)p.ent, L.ent.data(), 4 * L.ent.size());
+        up((void*)p.chunk, L.chunk.data(), 4 * L.chunk.size());
+        for (int a = 0; a <= L.S; ++a) p.chunk_base[a] = L.chunk_base[a];
         std::vector<double> cam((size_t)L.M * kCS, 0.0), lm((size_t)L.N * kLS, 0.0);
         const double sc = L.scale;
         for (int q = 0; q < L.M; ++q) {
