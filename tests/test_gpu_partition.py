@@ -118,3 +118,23 @@ def test_no_observations():
     st = g.get_state()
     np.testing.assert_allclose(st["cams"], prob["cameras"], rtol=0, atol=1e-12)
     np.testing.assert_allclose(st["lms"], prob["landmarks"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_properties():
+    """1,000 cameras, 1.6M observations, 8 partitions (the benchmark's
+    workload): F after every iteration equals the oracle's objective at the
+    GPU's iterate (the oracle's per-observation sums need no dense solve);
+    sum_a F^a(k) = F(x^k) (eq. Fak); plain MM descends."""
+    prob = make_problem("cam1k-lm200k")
+    print(f"partition full size: K={prob['n_obs']}", flush=True)
+    g = P.DabaPartSolver(prob, n_partitions=8, loss="huber")
+    F = g.iterate(3)
+    st = g.get_state()
+    o = PartOracle(prob, n_partitions=8, loss="huber")
+    x = (*o._cams_in(st["cams"]), st["lms"])
+    assert rel(F[-1], o.objective(x)) <= 1e-12
+    assert rel(st["metrics"][:, 0].sum(), F[-2]) <= 1e-11
+    mm = P.DabaPartSolver(prob, n_partitions=8, loss="huber", accelerate=False)
+    Fm = mm.iterate(4)
+    assert np.all(np.diff(Fm) <= 1e-12 * Fm[0])
