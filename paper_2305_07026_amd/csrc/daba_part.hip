@@ -736,8 +736,11 @@ __device__ __forceinline__ double lane_value(double x, int j) {
 
 // Blocked right-looking Cholesky, step k: factor the diagonal tile with one
 // wave, lane r holding row r in registers (column c: L_cc = sqrt(A_cc), the
-// rows below scale, then A_rj -= L_rc L_jc with L_jc broadcast from lane j).
-// The 64 loads of a row are issued together.
+// rows below scale, then A_rj -= L_rc L_jc with L_jc broadcast from lane j by
+// v_readlane).  Lanes above the diagonal (r < j) update entries of the upper
+// triangle, which start at zero and are never stored, so the update needs no
+// mask.  Scheduling barriers keep the broadcasts from being hoisted into an
+// SGPR spill.  The 64 loads of a row are issued together.
 __global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
     const int a = blockIdx.x;
     double* q = p.ps + (size_t)a * kPS;
@@ -759,9 +762,10 @@ __global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
         row[c] = r > c ? row[c] / l : (r == c ? l : row[c]);
 #pragma unroll
         for (int j = c + 1; j < kNB; ++j) {
-            const double ljc = lane_value(row[c], j);
-            row[j] = r >= j ? row[j] - row[c] * ljc : row[j];
+            row[j] -= row[c] * lane_value(row[c], j);
+            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
     if (r == 0 && bad) q[P_OK] = 0.0;
 #pragma unroll

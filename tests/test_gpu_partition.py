@@ -138,3 +138,17 @@ def test_full_size_properties():
     mm = P.DabaPartSolver(prob, n_partitions=8, loss="huber", accelerate=False)
     Fm = mm.iterate(4)
     assert np.all(np.diff(Fm) <= 1e-12 * Fm[0])
+
+
+@pytest.mark.timeout(600)
+def test_large_properties():
+    """5,000 cameras, 16M observations, 16 partitions (313 cameras each):
+    plain MM descends and sum_a F^a(k) = F(x^k) at this size."""
+    prob = make_problem("cam5k-lm2m")
+    print(f"partition large: K={prob['n_obs']}", flush=True)
+    g = P.DabaPartSolver(prob, n_partitions=16, loss="huber", accelerate=False)
+    F0 = g.iterate(1)
+    F = g.iterate(2)
+    Fs = np.r_[F0, F]
+    assert np.all(np.diff(Fs) <= 1e-12 * Fs[0])
+    assert rel(g.get_state()["metrics"][:, 0].sum(), Fs[-2]) <= 1e-11
