@@ -389,15 +389,23 @@ __global__ __launch_bounds__(64) void kp_init_metrics(PP p) {
     q[P_RESTART] = 0.0;
 }
 
-__global__ __launch_bounds__(64) void kp_lm_init(PP p) {
+// Start of an LM solve: every partition with unknowns, or (only_restarted)
+// only those whose restart test failed.  flag[0] = any partition active.
+__global__ __launch_bounds__(64) void kp_lm_init(PP p, int only_restarted) {
     const int a = threadIdx.x;
-    if (a >= p.S) return;
-    double* q = p.ps + (size_t)a * kPS;
-    q[P_MU] = 1e-4;
-    q[P_SUCC] = q[P_REJ] = 0.0;
-    q[P_ACTIVE] = (p.pc[a + 1] > p.pc[a] || p.pl[a + 1] > p.pl[a]) ? 1.0 : 0.0;
-    q[P_ACC] = 0.0;
-    q[P_OK] = 1.0;
+    int act = 0;
+    if (a < p.S) {
+        double* q = p.ps + (size_t)a * kPS;
+        q[P_MU] = 1e-4;
+        q[P_SUCC] = q[P_REJ] = 0.0;
+        act = (p.pc[a + 1] > p.pc[a] || p.pl[a + 1] > p.pl[a]) &&
+              (!only_restarted || q[P_RESTART] != 0.0);
+        q[P_ACTIVE] = act ? 1.0 : 0.0;
+        q[P_ACC] = 0.0;
+        q[P_OK] = 1.0;
+    }
+    const unsigned long long any = __ballot(act);
+    if (a == 0) p.flag[0] = any != 0ull ? 1 : 0;
 }
 
 // dst <- src for every camera and landmark (mask 0), or only for those whose
@@ -1048,15 +1056,15 @@ __global__ __launch_bounds__(64) void kp_accept(PP p) {
     if (a == 0) p.flag[0] = any != 0ull ? 1 : 0;
 }
 
-// Restart test (Algorithm 1; eq. Eak) from P_FK, P_FBAR, P_ECUR, P_EMM, P_EACC.
-__global__ __launch_bounds__(64) void kp_decide(PP p) {
+// Restart test (Algorithm 1; eq. Eak) from P_FK, P_FBAR, P_ECUR and P_EACC:
+// a partition keeps its accelerated step unless E^a(k+1) would exceed
+// Fbar^a(k); without acceleration every partition takes the plain step.
+__global__ __launch_bounds__(64) void kp_restart_test(PP p) {
     const int a = threadIdx.x;
     if (a >= p.S) return;
     double* q = p.ps + (size_t)a * kPS;
-    const double Emm = q[P_EMM] + q[P_FK] - q[P_ECUR];
     if (!p.accelerate) {
         q[P_RESTART] = 1.0;
-        q[P_E] = Emm;
         return;
     }
     const double Ehat = q[P_EACC] + q[P_FK] - q[P_ECUR];
@@ -1064,7 +1072,15 @@ __global__ __launch_bounds__(64) void kp_decide(PP p) {
     if (p.flags & DABA_DEBUG_NEVER_RESTART) rs = false;
     if (p.flags & DABA_DEBUG_ALWAYS_RESTART) rs = true;
     q[P_RESTART] = rs ? 1.0 : 0.0;
-    q[P_E] = rs ? Emm : Ehat;
+    if (!rs) q[P_E] = Ehat;
+}
+
+// E^a(k+1) of the partitions that take the plain step (eq. Eak with P_EMM).
+__global__ __launch_bounds__(64) void kp_restart_finish(PP p) {
+    const int a = threadIdx.x;
+    if (a >= p.S) return;
+    double* q = p.ps + (size_t)a * kPS;
+    if (q[P_RESTART] != 0.0) q[P_E] = q[P_EMM] + q[P_FK] - q[P_ECUR];
 }
 
 // x^(k-1) <- x^k; x^(k+1) <- the accelerated or the plain candidate.
@@ -1476,14 +1492,22 @@ void build_t(daba_part_handle* h, const double* yc, const double* yl) {
 }
 
 // Levenberg-Marquardt of every partition from y (P2 of the partition-level
-// reading); the result goes to (oc, ol).
-void lm_all(daba_part_handle* h, const double* yc, const double* yl, double* oc, double* ol) {
+// reading), or only of the partitions whose restart test failed; the result
+// goes to (oc, ol).  Returns false if no partition was solved.
+bool lm_all(daba_part_handle* h, const double* yc, const double* yl, double* oc, double* ol, bool only_restarted) {
     const PP& p = h->p;
     const Bufs& b = h->b;
     const unsigned ge = gdim(p.M + p.N, 64);
     {
         Timed t(h, C_REST);
-        hipLaunchKernelGGL(kp_lm_init, dim3(1), dim3(64), 0, h->stream, p);
+        hipLaunchKernelGGL(kp_lm_init, dim3(1), dim3(64), 0, h->stream, p, only_restarted ? 1 : 0);
+        hipck(hipGetLastError(), "LM init");
+        if (only_restarted) {  // nothing to solve when every partition kept its accelerated step
+            int any = 0;
+            hipck(hipMemcpyAsync(&any, p.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream), "flag copy");
+            hipck(hipStreamSynchronize(h->stream), "stream sync");
+            if (!any) return false;
+        }
         hipLaunchKernelGGL(kp_copy, dim3(ge), dim3(64), 0, h->stream, p, yc, yl, b.cur_c, b.cur_l, 0);
     }
     eval_reduce(h, b.cur_c, b.cur_l, yc, yl, EV_E, P_PHI);
@@ -1541,6 +1565,7 @@ void lm_all(daba_part_handle* h, const double* yc, const double* yl, double* oc,
     }
     Timed t(h, C_REST);
     hipLaunchKernelGGL(kp_copy, dim3(ge), dim3(64), 0, h->stream, p, b.cur_c, b.cur_l, oc, ol, 0);
+    return true;
 }
 
 void iterate(daba_part_handle* h, int n, double* F_trace) {
@@ -1561,14 +1586,23 @@ void iterate(daba_part_handle* h, int n, double* F_trace) {
                 Timed t(h, C_REST);
                 hipLaunchKernelGGL(kp_fk, dim3(1), dim3(64), 0, h->stream, p);
             }
-            lm_all(h, b.x_c, b.x_l, b.mm_c, b.mm_l);                  // eq. update_mm
-            if (p.accelerate) lm_all(h, b.xb_c, b.xb_l, b.ac_c, b.ac_l);  // eq. update_amm
+            // Algorithm 1: the accelerated step (eq. update_amm) first; the
+            // plain MM step (eq. update_mm) only for the partitions whose
+            // restart test fails (every partition without acceleration).
             eval_reduce(h, b.x_c, b.x_l, b.x_c, b.x_l, EV_E, P_ECUR);
-            eval_reduce(h, b.mm_c, b.mm_l, b.x_c, b.x_l, EV_E, P_EMM);
-            if (p.accelerate) eval_reduce(h, b.ac_c, b.ac_l, b.x_c, b.x_l, EV_E, P_EACC);
+            if (p.accelerate) {
+                lm_all(h, b.xb_c, b.xb_l, b.ac_c, b.ac_l, false);
+                eval_reduce(h, b.ac_c, b.ac_l, b.x_c, b.x_l, EV_E, P_EACC);
+            }
             {
                 Timed t(h, C_REST);
-                hipLaunchKernelGGL(kp_decide, dim3(1), dim3(64), 0, h->stream, p);
+                hipLaunchKernelGGL(kp_restart_test, dim3(1), dim3(64), 0, h->stream, p);
+            }
+            if (lm_all(h, b.x_c, b.x_l, b.mm_c, b.mm_l, true))
+                eval_reduce(h, b.mm_c, b.mm_l, b.x_c, b.x_l, EV_E, P_EMM);
+            {
+                Timed t(h, C_REST);
+                hipLaunchKernelGGL(kp_restart_finish, dim3(1), dim3(64), 0, h->stream, p);
                 hipLaunchKernelGGL(kp_roll, dim3(ge), dim3(64), 0, h->stream, p, b.x_c, b.xp_c, b.mm_c, b.ac_c, b.x_l,
                                    b.xp_l, b.mm_l, b.ac_l);
             }
