@@ -19,8 +19,19 @@
 //   kp_trsv        L L^T dc = b per partition;
 //   kp_step        dl = -W g_l - sum T^T dc per landmark; retraction
 //                  R Exp(dtheta), t + dt, d + dd, l + dl;
-//   kp_eval + kp_reduce   E^a at the trial point (fixed-order sums);
-//   kp_accept, kp_commit  strict-decrease test and damping update.
+//   kp_eval + kp_reduce1/2   E^a at the trial point (fixed-order sums over
+//                  chunks of each partition's observations);
+//   kp_accept + kp_copy      strict-decrease test, damping update, and the
+//                  accepted trial becomes the LM point.
+// The host loops over attempts until every partition has its successful
+// steps or gives up (one stream synchronization per attempt).
+//
+// One iteration (Algorithm 1): kp_nesterov and kp_extrap (x-bar), the gap of
+// eq. DEalpha at (x^k | x^(k-1)) and eq. Fak / lFak (kp_fk), the LM solve of
+// the accelerated surrogate for every partition, the restart test
+// (kp_restart_test), the LM solve of the plain surrogate only for the
+// partitions that fail it, eq. Eak for them (kp_restart_finish), kp_roll,
+// and F at the new iterate (kp_trace).
 // All FP64.  No atomics: results are bitwise reproducible.
 
 #include <hip/hip_runtime.h>
@@ -742,39 +753,120 @@ __device__ __forceinline__ double lane_value(double x, int j) {
     return __builtin_bit_cast(double, o);
 }
 
+typedef __attribute__((address_space(3))) double lds_double;
+
+// LDS accesses of the diagonal factorisation as volatile asm statements:
+// they keep their program order among themselves (which is all the ordering
+// the column exchange needs), and every read waits for its data inside the
+// statement, so no result is used early and no read is hoisted.  No memory
+// clobber: the row held in registers must stay in registers.
+// lds_read8: eight doubles at LDS byte address addr (the same for every lane:
+// a broadcast).
+__device__ __forceinline__ void lds_read8(unsigned addr, double* v) {
+    asm volatile(
+        "ds_read_b64 %0, %8\n\t"
+        "ds_read_b64 %1, %8 offset:8\n\t"
+        "ds_read_b64 %2, %8 offset:16\n\t"
+        "ds_read_b64 %3, %8 offset:24\n\t"
+        "ds_read_b64 %4, %8 offset:32\n\t"
+        "ds_read_b64 %5, %8 offset:40\n\t"
+        "ds_read_b64 %6, %8 offset:48\n\t"
+        "ds_read_b64 %7, %8 offset:56\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]), "=&v"(v[7])
+        : "v"(addr));
+}
+
+__device__ __forceinline__ double lds_read1(unsigned addr) {
+    double v;
+    asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(v) : "v"(addr));
+    return v;
+}
+
+__device__ __forceinline__ void lds_write1(unsigned addr, double v) {
+    asm volatile("ds_write_b64 %0, %1" : : "v"(addr), "v"(v));
+}
+
+// x_jj -= rc * (eight doubles at LDS byte address addr), reads and updates in
+// one statement, so that no read result outlives its update.
+__device__ __forceinline__ void lds_fnma8(unsigned addr, double rc, double& x0, double& x1, double& x2,
+                                          double& x3, double& x4, double& x5, double& x6, double& x7) {
+    double t0, t1, t2, t3, t4, t5, t6, t7;
+    asm volatile(
+        "ds_read_b64 %8, %16\n\t"
+        "ds_read_b64 %9, %16 offset:8\n\t"
+        "ds_read_b64 %10, %16 offset:16\n\t"
+        "ds_read_b64 %11, %16 offset:24\n\t"
+        "ds_read_b64 %12, %16 offset:32\n\t"
+        "ds_read_b64 %13, %16 offset:40\n\t"
+        "ds_read_b64 %14, %16 offset:48\n\t"
+        "ds_read_b64 %15, %16 offset:56\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_fma_f64 %0, -%17, %8, %0\n\t"
+        "v_fma_f64 %1, -%17, %9, %1\n\t"
+        "v_fma_f64 %2, -%17, %10, %2\n\t"
+        "v_fma_f64 %3, -%17, %11, %3\n\t"
+        "v_fma_f64 %4, -%17, %12, %4\n\t"
+        "v_fma_f64 %5, -%17, %13, %5\n\t"
+        "v_fma_f64 %6, -%17, %14, %6\n\t"
+        "v_fma_f64 %7, -%17, %15, %7"
+        : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3), "+v"(x4), "+v"(x5), "+v"(x6), "+v"(x7),
+          "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(t4), "=&v"(t5), "=&v"(t6), "=&v"(t7)
+        : "v"(addr), "v"(rc));
+}
+
+// Column C of the diagonal factorisation (compile-time recursion, so that
+// every index into the row is a constant and the row stays in registers).
+template <int C>
+__device__ __forceinline__ void chol_column(double (&row)[kNB], int r, unsigned cbase, bool& bad) {
+    lds_write1(cbase + 8 * r, row[C]);
+    const double d = lds_read1(cbase + 8 * C);
+    bad = bad || !(d > 0.0);
+    const double l = d > 0.0 ? sqrt(d) : 1.0;
+    row[C] = r > C ? row[C] / l : (r == C ? l : row[C]);
+    lds_write1(cbase + 8 * r, row[C]);
+    constexpr int g0 = (C + 1) / 8;  // the group holding column C + 1
+    if constexpr (g0 < kNB / 8) {
+        if constexpr ((C + 1) % 8 != 0) {  // partly left of the pivot: masked
+            double L[8];
+            lds_read8(cbase + 64 * g0, L);
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                if (8 * g0 + jj > C) row[8 * g0 + jj] -= row[C] * L[jj];
+        }
+        constexpr int gfull = (C + 1) % 8 != 0 ? g0 + 1 : g0;
+#pragma unroll
+        for (int g = gfull; g < kNB / 8; ++g)
+            lds_fnma8(cbase + 64 * g, row[C], row[8 * g], row[8 * g + 1], row[8 * g + 2], row[8 * g + 3],
+                      row[8 * g + 4], row[8 * g + 5], row[8 * g + 6], row[8 * g + 7]);
+    }
+    if constexpr (C + 1 < kNB) chol_column<C + 1>(row, r, cbase, bad);
+}
+
 // Blocked right-looking Cholesky, step k: factor the diagonal tile with one
-// wave, lane r holding row r in registers (column c: L_cc = sqrt(A_cc), the
-// rows below scale, then A_rj -= L_rc L_jc with L_jc broadcast from lane j by
-// v_readlane).  Lanes above the diagonal (r < j) update entries of the upper
-// triangle, which start at zero and are never stored, so the update needs no
-// mask.  Scheduling barriers keep the broadcasts from being hoisted into an
-// SGPR spill.  The 64 loads of a row are issued together.
+// wave, lane r holding row r in registers.  Column c: every lane publishes
+// A_rc in LDS and reads the pivot; the rows below scale to L_rc and publish
+// it; every lane then takes L_rc L_jc out of A_rj (j > c), reading L_jc by
+// broadcast, eight at a time.  A wave's LDS accesses complete in program
+// order, so no barrier is needed.  Lanes above the diagonal (r < j) update
+// entries of the upper triangle, which start at zero and are never stored,
+// so the update needs no mask.  The 64 loads of a row are issued together.
 __global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
+    __shared__ double col[kNB];
     const int a = blockIdx.x;
     double* q = p.ps + (size_t)a * kPS;
     if (q[P_ACTIVE] == 0.0 || k >= p.nt[a]) return;
     const int np = p.npad[a];
     double* Sr = p.Smat + p.soff[a] + (size_t)(kNB * k + threadIdx.x) * np + kNB * k;
     const int r = threadIdx.x;
+    const unsigned cbase = (unsigned)(size_t)(lds_double*)col;
     double row[kNB];
 #pragma unroll
     for (int m = 0; m < kNB; ++m) row[m] = Sr[m];
 #pragma unroll
     for (int m = 0; m < kNB; ++m) row[m] = m <= r ? row[m] : 0.0;
     bool bad = false;
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-        const double d = lane_value(row[c], c);
-        bad = bad || !(d > 0.0);
-        const double l = d > 0.0 ? sqrt(d) : 1.0;
-        row[c] = r > c ? row[c] / l : (r == c ? l : row[c]);
-#pragma unroll
-        for (int j = c + 1; j < kNB; ++j) {
-            row[j] -= row[c] * lane_value(row[c], j);
-            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    chol_column<0>(row, r, cbase, bad);
     if (r == 0 && bad) q[P_OK] = 0.0;
 #pragma unroll
     for (int m = 0; m < kNB; ++m)
