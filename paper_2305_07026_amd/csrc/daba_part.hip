@@ -860,6 +860,8 @@ __global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
     double* Sr = p.Smat + p.soff[a] + (size_t)(kNB * k + threadIdx.x) * np + kNB * k;
     const int r = threadIdx.x;
     const unsigned cbase = (unsigned)(size_t)(lds_double*)col;
+    double* bk = p.vec + p.voff[a] + kNB * k;
+    double y = bk[r];  // right-hand side entry r of this tile, reduced by the earlier tiles
     double row[kNB];
 #pragma unroll
     for (int m = 0; m < kNB; ++m) row[m] = Sr[m];
@@ -871,6 +873,15 @@ __global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
 #pragma unroll
     for (int m = 0; m < kNB; ++m)
         if (m <= r) Sr[m] = row[m];
+    // forward substitution folded into the factorisation: L_kk y = b_k here,
+    // and the panel step takes L_ik y_k out of b_i for the tiles below
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) {
+        if (r == c) lds_write1(cbase, y / row[c]);
+        const double yc = lds_read1(cbase);
+        y = r == c ? yc : (r > c ? y - row[c] * yc : y);
+    }
+    bk[r] = y;
 }
 
 // Step k: L_ik = A_ik L_kk^-T for every tile row i > k.  Lane r solves row r
@@ -878,6 +889,7 @@ __global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
 // staged in LDS and read by broadcast.
 __global__ __launch_bounds__(64) void kp_chol_trsm(PP p, int k) {
     __shared__ double L[kNB][kNB + 1];
+    __shared__ double yk[kNB];
     const int a = blockIdx.y;
     const int i = k + 1 + blockIdx.x;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0 || i >= p.nt[a]) return;
@@ -895,6 +907,8 @@ __global__ __launch_bounds__(64) void kp_chol_trsm(PP p, int k) {
 #pragma unroll
         for (int rr = 0; rr < kNB; ++rr) L[rr][t] = col[rr];
     }
+    double* b = p.vec + p.voff[a];
+    yk[t] = b[kNB * k + t];  // y_k, solved by the diagonal step
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kNB; ++c) {
@@ -905,6 +919,14 @@ __global__ __launch_bounds__(64) void kp_chol_trsm(PP p, int k) {
     }
 #pragma unroll
     for (int m = 0; m < kNB; ++m) Ar[m] = x[m];
+    // forward substitution of the right-hand side: b_i -= L_ik y_k
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kNB; c += 2) {
+        s0 += x[c] * yk[c];
+        s1 += x[c + 1] * yk[c + 1];
+    }
+    b[kNB * i + t] -= s0 + s1;
 }
 
 // Step k: A_ij -= L_ik L_jk^T for tiles k < j <= i; the inner dimension in
@@ -967,11 +989,11 @@ __global__ __launch_bounds__(256) void kp_chol_update(PP p, int k) {
         for (int v = 0; v < 4; ++v) Aij[(size_t)(r0 + u) * np + c0 + v] -= acc[u][v];
 }
 
-// L L^T x = b in place on the partition's vector, one 64-row tile at a time:
-// solve the tile's triangle in registers (one wave, lane = row), then take
-// the solved values out of the rest of the right-hand side (forward: one lane
-// per row below the tile, reading its 64 entries; backward: one lane per row
-// above the tile, reading the tile's rows of L, consecutive across lanes).
+// L^T x = y in place on the partition's vector (the forward half, L y = b,
+// is folded into the factorisation), one 64-row tile at a time from the
+// last: solve the tile's triangle in registers (one wave, lane = row), then
+// take the solved values out of the rows above (one lane per row, reading
+// the tile's rows of L, consecutive across lanes).
 __global__ __launch_bounds__(256) void kp_trsv(PP p) {
     __shared__ double xs[kNB];
     __shared__ double D[kNB][kNB + 1];  // the current diagonal tile
@@ -981,52 +1003,6 @@ __global__ __launch_bounds__(256) void kp_trsv(PP p) {
     const double* L = p.Smat + p.soff[a];
     double* b = p.vec + p.voff[a];
     const int tid = threadIdx.x;
-    for (int kt = 0; kt < nt; ++kt) {
-        const int c0 = kNB * kt;
-        if (tid < kNB) xs[tid] = b[c0 + tid];
-        {
-            double v[kNB * kNB / 256];
-#pragma unroll
-            for (int u = 0; u < kNB * kNB / 256; ++u) {
-                const int e = tid + 256 * u;
-                v[u] = L[(size_t)(c0 + e / kNB) * np + c0 + e % kNB];
-            }
-#pragma unroll
-            for (int u = 0; u < kNB * kNB / 256; ++u) {
-                const int e = tid + 256 * u;
-                D[e / kNB][e % kNB] = v[u];
-            }
-        }
-        __syncthreads();
-        if (tid < kNB) {  // wave 0, lane = row of the tile: forward sweep in registers
-            double xv = xs[tid];
-            double drow[kNB];
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) drow[c] = D[tid][c];
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) {
-                const double xc = lane_value(xv, c) / lane_value(drow[c], c);
-                xv = tid == c ? xc : (tid > c ? xv - drow[c] * xc : xv);
-            }
-            xs[tid] = xv;
-            b[c0 + tid] = xv;
-        }
-        __syncthreads();
-        for (int r = c0 + kNB + tid; r < np; r += 256) {
-            const double* Lr = L + (size_t)r * np + c0;
-            double v[kNB];
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) v[c] = Lr[c];
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int c = 0; c < kNB; c += 2) {
-                s0 += v[c] * xs[c];
-                s1 += v[c + 1] * xs[c + 1];
-            }
-            b[r] -= s0 + s1;
-        }
-        __syncthreads();
-    }
     for (int kt = nt - 1; kt >= 0; --kt) {
         const int c0 = kNB * kt;
         if (tid < kNB) xs[tid] = b[c0 + tid];
@@ -1833,6 +1809,9 @@ int daba_part_create(const daba_problem* prob, const daba_options* opt, void* de
         for (double* d : {b.x_l, b.xp_l, b.xb_l, b.mm_l, b.ac_l, b.cur_l, b.try_l}) up(d, lm.data(), 8 * lm.size());
         if (L.smat_total > 0)
             hipLaunchKernelGGL(kp_init_smat, dim3(gdim(L.smat_total, 256)), dim3(256), 0, s, p, L.smat_total);
+        // the padding entries of the right-hand sides are never written and
+        // must be zero (they meet zero rows of L in the substitutions)
+        if (L.vec_total > 0) hipck(hipMemsetAsync(p.vec, 0, sizeof(double) * (size_t)L.vec_total, s), "memset");
         hipck(hipGetLastError(), "init");
         for (auto& e : h->ev) hipck(hipEventCreate(&e), "event create");
         eval_reduce(h, b.x_c, b.x_l, b.x_c, b.x_l, EV_E, P_RED);  // eq. Fainit
