@@ -156,3 +156,15 @@ def test_part_create_rejects_before_device_work(prob, case):
     assert rc == (-5 if case == "degenerate" else -1), (case, rc, B.lib.daba_part_last_error(None))
     assert not h.value
     assert B.lib.daba_part_last_error(None)
+
+
+def test_part_rejects_a_partition_beyond_the_camera_limit():
+    import ctypes as C
+    big = make_problem("cam50-lm5k", n_cameras=2100, n_landmarks=200, seed=3)
+    keep, pr, opt = _part_args(big, n_partitions=1)
+    assert B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt)) == 0
+    h = C.c_void_p()
+    assert B.lib.daba_part_create(C.byref(pr), C.byref(opt), None, 0, None, C.byref(h)) == -1
+    assert b"at most" in B.lib.daba_part_last_error(None)
+    keep, pr, opt = _part_args(big, n_partitions=2)  # 1,050 cameras each: accepted
+    assert B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt)) > 0
