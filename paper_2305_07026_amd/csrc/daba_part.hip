@@ -815,6 +815,53 @@ __device__ __forceinline__ void lds_fnma8(unsigned addr, double rc, double& x0, 
         : "v"(addr), "v"(rc));
 }
 
+// Two groups of eight in one statement: the second group's reads are in
+// flight while the first group's updates run (lgkmcnt(8) waits for the
+// oldest eight reads only).
+__device__ __forceinline__ void lds_fnma16(unsigned addr, double rc, double* x) {
+    double t0, t1, t2, t3, t4, t5, t6, t7, u0, u1, u2, u3, u4, u5, u6, u7;
+    asm volatile(
+        "ds_read_b64 %16, %32\n\t"
+        "ds_read_b64 %17, %32 offset:8\n\t"
+        "ds_read_b64 %18, %32 offset:16\n\t"
+        "ds_read_b64 %19, %32 offset:24\n\t"
+        "ds_read_b64 %20, %32 offset:32\n\t"
+        "ds_read_b64 %21, %32 offset:40\n\t"
+        "ds_read_b64 %22, %32 offset:48\n\t"
+        "ds_read_b64 %23, %32 offset:56\n\t"
+        "ds_read_b64 %24, %32 offset:64\n\t"
+        "ds_read_b64 %25, %32 offset:72\n\t"
+        "ds_read_b64 %26, %32 offset:80\n\t"
+        "ds_read_b64 %27, %32 offset:88\n\t"
+        "ds_read_b64 %28, %32 offset:96\n\t"
+        "ds_read_b64 %29, %32 offset:104\n\t"
+        "ds_read_b64 %30, %32 offset:112\n\t"
+        "ds_read_b64 %31, %32 offset:120\n\t"
+        "s_waitcnt lgkmcnt(8)\n\t"
+        "v_fma_f64 %0, -%33, %16, %0\n\t"
+        "v_fma_f64 %1, -%33, %17, %1\n\t"
+        "v_fma_f64 %2, -%33, %18, %2\n\t"
+        "v_fma_f64 %3, -%33, %19, %3\n\t"
+        "v_fma_f64 %4, -%33, %20, %4\n\t"
+        "v_fma_f64 %5, -%33, %21, %5\n\t"
+        "v_fma_f64 %6, -%33, %22, %6\n\t"
+        "v_fma_f64 %7, -%33, %23, %7\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "v_fma_f64 %8, -%33, %24, %8\n\t"
+        "v_fma_f64 %9, -%33, %25, %9\n\t"
+        "v_fma_f64 %10, -%33, %26, %10\n\t"
+        "v_fma_f64 %11, -%33, %27, %11\n\t"
+        "v_fma_f64 %12, -%33, %28, %12\n\t"
+        "v_fma_f64 %13, -%33, %29, %13\n\t"
+        "v_fma_f64 %14, -%33, %30, %14\n\t"
+        "v_fma_f64 %15, -%33, %31, %15"
+        : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
+          "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]), "+v"(x[14]), "+v"(x[15]),
+          "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(t4), "=&v"(t5), "=&v"(t6), "=&v"(t7),
+          "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3), "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7)
+        : "v"(addr), "v"(rc));
+}
+
 // Column C of the diagonal factorisation (compile-time recursion, so that
 // every index into the row is a constant and the row stays in registers).
 template <int C>
@@ -835,10 +882,15 @@ __device__ __forceinline__ void chol_column(double (&row)[kNB], int r, unsigned 
                 if (8 * g0 + jj > C) row[8 * g0 + jj] -= row[C] * L[jj];
         }
         constexpr int gfull = (C + 1) % 8 != 0 ? g0 + 1 : g0;
+        constexpr int npair = (kNB / 8 - gfull) / 2;
 #pragma unroll
-        for (int g = gfull; g < kNB / 8; ++g)
+        for (int u = 0; u < npair; ++u)  // full groups two at a time
+            lds_fnma16(cbase + 64 * (gfull + 2 * u), row[C], &row[8 * (gfull + 2 * u)]);
+        if constexpr ((kNB / 8 - gfull) % 2 != 0) {
+            constexpr int g = kNB / 8 - 1;
             lds_fnma8(cbase + 64 * g, row[C], row[8 * g], row[8 * g + 1], row[8 * g + 2], row[8 * g + 3],
                       row[8 * g + 4], row[8 * g + 5], row[8 * g + 6], row[8 * g + 7]);
+        }
     }
     if constexpr (C + 1 < kNB) chol_column<C + 1>(row, r, cbase, bad);
 }
