@@ -1892,6 +1892,9 @@ int daba_part_iterate(daba_part_handle* h, int n_iters, double* F_trace) {
     } catch (const Fail& f) {
         h->err = f.msg;
         return f.code;
+    } catch (const std::bad_alloc&) {
+        h->err = "host allocation failed";
+        return DABA_E_NOMEM;
     }
 }
 
@@ -1916,6 +1919,9 @@ int daba_part_iterate_timed(daba_part_handle* h, int n_iters, double* ms_out) {
     } catch (const Fail& f) {
         h->err = f.msg;
         return f.code;
+    } catch (const std::bad_alloc&) {
+        h->err = "host allocation failed";
+        return DABA_E_NOMEM;
     }
 }
 
@@ -1959,6 +1965,9 @@ int daba_part_get_state(daba_part_handle* h, double* cams, double* lms, double* 
     } catch (const Fail& f) {
         h->err = f.msg;
         return f.code;
+    } catch (const std::bad_alloc&) {
+        h->err = "host allocation failed";
+        return DABA_E_NOMEM;
     }
 }
 
