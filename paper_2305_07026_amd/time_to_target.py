@@ -15,7 +15,7 @@ Here F_ref(p) for a loss is the lowest objective that any run on p with that
 loss reaches within the iteration budget, over every partition count and
 both methods.
 
-    python -m paper_2305_07026_amd.time_to_target [--budget 2000] [--out FILE]
+    python -m paper_2305_07026_amd.time_to_target [--budget 2000] [--out FILE] [--surrogate device]
 """
 
 from __future__ import annotations
@@ -77,10 +77,22 @@ def default_suite(seeds=(11, 12, 13, 14, 15)):
 
 
 def gpu_runner(prob: dict, accelerate: bool, loss: str, S: int, budget: int):
-    """(F at x^0, F after each of `budget` iterations) on the GPU path."""
+    """(F at x^0, F after each of `budget` iterations) on the GPU path with
+    the entity-level surrogate."""
     from .solver import DabaSolver
     sol = DabaSolver(prob, n_partitions=S, loss=loss, delta=1.0, accelerate=accelerate)
     F0 = sol.objective()
+    trace = sol.iterate(budget)
+    sol.close()
+    return F0, trace
+
+
+def gpu_runner_device(prob: dict, accelerate: bool, loss: str, S: int, budget: int):
+    """The same with the device-level surrogate of eq. Ealpha (intra-partition
+    pairs exact, one LM solve per partition)."""
+    from .solver import DabaPartSolver, DabaSolver
+    F0 = DabaSolver(prob, n_partitions=S, loss=loss, delta=1.0).objective()
+    sol = DabaPartSolver(prob, n_partitions=S, loss=loss, delta=1.0, accelerate=accelerate)
     trace = sol.iterate(budget)
     sol.close()
     return F0, trace
@@ -154,9 +166,13 @@ def main():
     ap.add_argument("--budget", type=int, default=2000)
     ap.add_argument("--delta", type=float, default=1e-4)
     ap.add_argument("--out", default=None, help="write the full result as JSON")
+    ap.add_argument("--surrogate", default="entity", choices=["entity", "device"],
+                    help="entity: every pair majorized; device: the surrogate of eq. Ealpha (include/daba_part.h)")
     args = ap.parse_args()
     t0 = time.time()
-    res = run(default_suite(), budget=args.budget, delta=args.delta, log=lambda s: print(s, flush=True))
+    runner = gpu_runner_device if args.surrogate == "device" else gpu_runner
+    res = run(default_suite(), budget=args.budget, delta=args.delta, runner=runner,
+              log=lambda s: print(s, flush=True))
     print(summary(res))
     print(f"({len(res['records'])} comparisons in {time.time() - t0:.0f} s)")
     if args.out:
