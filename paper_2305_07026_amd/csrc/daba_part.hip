@@ -1378,14 +1378,23 @@ void build_layout(const daba_problem* pr, PLayout& L) {
     for (int a = 0; a < S; ++a)
         if (L.pc[a + 1] - L.pc[a] > DABA_PART_MAX_CAMERAS)
             fail(DABA_E_INVAL, "partition %d has %d cameras (at most %d)", a, L.pc[a + 1] - L.pc[a], DABA_PART_MAX_CAMERAS);
-    // observations in (internal camera, internal landmark, caller index) order
+    // observations in (internal camera, internal landmark, caller index)
+    // order: a stable counting sort by landmark, then one by camera
     std::vector<int64_t> ord(K);
-    for (int64_t o = 0; o < K; ++o) ord[o] = o;
-    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
-        const int cx = L.cam_int[pr->obs_camera[x]], cy = L.cam_int[pr->obs_camera[y]];
-        if (cx != cy) return cx < cy;
-        return L.lm_int[pr->obs_landmark[x]] < L.lm_int[pr->obs_landmark[y]];
-    });
+    {
+        std::vector<int64_t> tmp(K), cnt((size_t)std::max(M, N) + 1);
+        std::fill(cnt.begin(), cnt.begin() + N + 1, 0);
+        for (int64_t o = 0; o < K; ++o) cnt[L.lm_int[pr->obs_landmark[o]] + 1]++;
+        for (int j = 0; j < N; ++j) cnt[j + 1] += cnt[j];
+        for (int64_t o = 0; o < K; ++o) tmp[cnt[L.lm_int[pr->obs_landmark[o]]]++] = o;
+        std::fill(cnt.begin(), cnt.begin() + M + 1, 0);
+        for (int64_t o = 0; o < K; ++o) cnt[L.cam_int[pr->obs_camera[o]] + 1]++;
+        for (int i = 0; i < M; ++i) cnt[i + 1] += cnt[i];
+        for (int64_t q = 0; q < K; ++q) {
+            const int64_t o = tmp[q];
+            ord[cnt[L.cam_int[pr->obs_camera[o]]]++] = o;
+        }
+    }
     L.ocam.resize(K);
     L.olm.resize(K);
     L.ointra.resize(K);
@@ -1440,13 +1449,13 @@ void build_layout(const daba_problem* pr, PLayout& L) {
     for (int pass = 0; pass < 2; ++pass) {
         std::vector<int64_t> fill;
         if (pass == 1) fill.assign(cnt.begin(), cnt.end() - 1);
+        int a = 0;
         for (int j = 0; j < N; ++j) {
+            while (a + 1 < S && L.pl[a + 1] <= j) ++a;  // landmarks are in partition order
             ex.clear();
             for (int k = L.lm_off[j]; k < L.lm_off[j + 1]; ++k)
                 if (L.ointra[L.lm_obs[k]]) ex.push_back(L.lm_obs[k]);
             if (ex.empty()) continue;
-            int a = 0;
-            while (a + 1 < S && L.pl[a + 1] <= j) ++a;
             for (int o1 : ex)
                 for (int o2 : ex) {
                     const int q1 = L.ocam[o1] - L.pc[a], q2 = L.ocam[o2] - L.pc[a];

@@ -152,3 +152,16 @@ def test_large_properties():
     Fs = np.r_[F0, F]
     assert np.all(np.diff(Fs) <= 1e-12 * Fs[0])
     assert rel(g.get_state()["metrics"][:, 0].sum(), Fs[-2]) <= 1e-11
+
+
+@pytest.mark.parametrize("xi,scale", [(0.05, 256.0), (2.0, 512.0)])
+def test_proximal_term_matters(small, xi, scale):
+    """With a large xi the proximal term (its rotation gradient and the xi I
+    of the model Hessian, reading P4) shapes every step; with another unit
+    scale the unit conversions are exercised too."""
+    g, o, Fg, Fo, st, mo = run_both(small, 6, n_partitions=3, loss="huber", xi=xi, unit_scale=scale)
+    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
+    c_o, l_o = o.get_state()
+    assert nrel(st["lms"], l_o) <= 1e-6
+    assert nrel(st["cams"][:, :12], c_o[:, :12]) <= 1e-6
+    np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
