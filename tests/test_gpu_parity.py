@@ -80,6 +80,20 @@ def test_free_running_parity_tiled(tiled):
     assert (np.abs(Fg - Fo) / Fo).max() <= 1e-10
 
 
+@pytest.mark.parametrize("xi,scale", [(0.05, 256.0), (2.0, 512.0)])
+def test_free_running_parity_large_prox(tiled, xi, scale):
+    """A proximal weight that shapes every camera and landmark solve (the
+    rotation prox of the camera LM, the xi terms of the landmark closed
+    form), with another unit scale."""
+    g, o = both(tiled, n_partitions=3, loss="huber", xi=xi, unit_scale=scale)
+    Fg = g.iterate(40)
+    Fo, mo = o.iterate(40)
+    assert (np.abs(Fg - Fo) / Fo).max() <= 1e-10
+    mg = g.metrics()
+    assert rel(mg[:, :3], mo[-1, :, :3]) <= 1e-9
+    assert np.array_equal(mg[:, 3], mo[-1, :, 3])
+
+
 @pytest.mark.parametrize("loss", ["trivial", "welsch"])
 def test_free_running_parity_other_losses(tiled, loss):
     """The other two losses of Assumption 1 (Welsch is non-convex): F after
