@@ -165,3 +165,13 @@ def test_proximal_term_matters(small, xi, scale):
     assert nrel(st["lms"], l_o) <= 1e-6
     assert nrel(st["cams"][:, :12], c_o[:, :12]) <= 1e-6
     np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
+
+
+@pytest.mark.parametrize("loss,eta", [("trivial", 1.0), ("huber", 1.0), ("welsch", 0.25)])
+def test_restart_average_weights(small, loss, eta):
+    """eq. lFak with other weights eta (eta = 1: the test compares with
+    F^a(k) itself) and the trivial loss under acceleration."""
+    g, o, Fg, Fo, st, mo = run_both(small, 10, n_partitions=3, loss=loss, eta=eta)
+    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
+    np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
+    assert rel(st["metrics"][:, :3], mo[-1, :, :3]) <= 1e-8
