@@ -70,6 +70,18 @@ int daba_part_get_state(daba_part_handle *h, double *cams, double *lms, double *
  * total is slower than daba_part_iterate. */
 int daba_part_iterate_timed(daba_part_handle *h, int n_iters, double *ms_out);
 
+/* Checkpoint of everything the next iteration depends on (Sec. V): x^k and
+ * x^(k-1) (HOST cams [M*15], lms [N*3], cams_prev, lms_prev; caller units
+ * and order) and per partition part3 [S*3] = (Fbar^a(k-1), E^a(k) in
+ * pixels^2, s^a(k)).  Any pointer may be NULL.  get synchronizes; set
+ * replaces the given parts (rotations are not re-validated) and enqueues
+ * the uploads, so that a handle created for the same problem and options
+ * continues exactly where the checkpoint was taken. */
+int daba_part_get_checkpoint(daba_part_handle *h, double *cams, double *lms, double *cams_prev,
+                             double *lms_prev, double *part3);
+int daba_part_set_checkpoint(daba_part_handle *h, const double *cams, const double *lms,
+                             const double *cams_prev, const double *lms_prev, const double *part3);
+
 int daba_part_destroy(daba_part_handle *h);
 
 /* Text of the last error on this handle (or of the last failed create when h

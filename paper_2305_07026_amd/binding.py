@@ -87,13 +87,15 @@ def _load() -> C.CDLL:
     lib.daba_part_iterate.argtypes = [vp, i, pd]
     lib.daba_part_iterate_timed.argtypes = [vp, i, pd]
     lib.daba_part_get_state.argtypes = [vp, pd, pd, pd]
+    lib.daba_part_get_checkpoint.argtypes = [vp, pd, pd, pd, pd, pd]
+    lib.daba_part_set_checkpoint.argtypes = [vp, pd, pd, pd, pd, pd]
     lib.daba_part_destroy.argtypes = [vp]
     lib.daba_part_last_error.argtypes = [vp]
     lib.daba_part_last_error.restype = C.c_char_p
     for name in ("daba_create", "daba_iterate", "daba_iterate_timed", "daba_objective", "daba_grad",
                  "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy", "daba_stream_copy",
                  "daba_part_create", "daba_part_iterate", "daba_part_iterate_timed", "daba_part_get_state",
-                 "daba_part_destroy"):
+                 "daba_part_get_checkpoint", "daba_part_set_checkpoint", "daba_part_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
 

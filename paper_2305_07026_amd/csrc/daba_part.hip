@@ -1980,6 +1980,132 @@ int daba_part_get_state(daba_part_handle* h, double* cams, double* lms, double* 
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+void download_cams(daba_part_handle* h, const double* dev, double* out) {
+    const PLayout& L = h->L;
+    const double sc = L.scale;
+    std::vector<double> c((size_t)L.M * kCS);
+    hipck(hipMemcpy(c.data(), dev, 8 * c.size(), hipMemcpyDeviceToHost), "download");
+    for (int q = 0; q < L.M; ++q) {
+        const double* s = &c[(size_t)q * kCS];
+        double* d = out + 15 * (size_t)L.cam_ext[q];
+        for (int a = 0; a < 12; ++a) d[a] = s[a];
+        d[12] = s[12] * sc;
+        d[13] = s[13] / sc;
+        d[14] = s[14] / (sc * sc * sc);
+    }
+}
+
+void download_lms(daba_part_handle* h, const double* dev, double* out) {
+    const PLayout& L = h->L;
+    std::vector<double> l((size_t)L.N * kLS);
+    hipck(hipMemcpy(l.data(), dev, 8 * l.size(), hipMemcpyDeviceToHost), "download");
+    for (int q = 0; q < L.N; ++q)
+        for (int a = 0; a < 3; ++a) out[3 * (size_t)L.lm_ext[q] + a] = l[(size_t)q * kLS + a];
+}
+
+void upload_cams(daba_part_handle* h, const double* in, double* dev) {
+    const PLayout& L = h->L;
+    const double sc = L.scale;
+    std::vector<double> c((size_t)L.M * kCS, 0.0);
+    for (int q = 0; q < L.M; ++q) {
+        const double* s = in + 15 * (size_t)L.cam_ext[q];
+        double* d = &c[(size_t)q * kCS];
+        for (int a = 0; a < 15; ++a)
+            if (!std::isfinite(s[a])) fail(DABA_E_INVAL, "camera %d has a non-finite entry", L.cam_ext[q]);
+        for (int a = 0; a < 12; ++a) d[a] = s[a];
+        d[12] = s[12] / sc;
+        d[13] = s[13] * sc;
+        d[14] = s[14] * sc * sc * sc;
+    }
+    hipck(hipMemcpyAsync(dev, c.data(), 8 * c.size(), hipMemcpyHostToDevice, h->stream), "upload");
+    hipck(hipStreamSynchronize(h->stream), "stream sync");  // the staging vector goes out of scope
+}
+
+void upload_lms(daba_part_handle* h, const double* in, double* dev) {
+    const PLayout& L = h->L;
+    std::vector<double> l((size_t)L.N * kLS, 0.0);
+    for (int q = 0; q < L.N; ++q)
+        for (int a = 0; a < 3; ++a) {
+            const double v = in[3 * (size_t)L.lm_ext[q] + a];
+            if (!std::isfinite(v)) fail(DABA_E_INVAL, "landmark %d has a non-finite entry", L.lm_ext[q]);
+            l[(size_t)q * kLS + a] = v;
+        }
+    hipck(hipMemcpyAsync(dev, l.data(), 8 * l.size(), hipMemcpyHostToDevice, h->stream), "upload");
+    hipck(hipStreamSynchronize(h->stream), "stream sync");
+}
+
+}  // namespace
+
+extern "C" {
+
+int daba_part_get_checkpoint(daba_part_handle* h, double* cams, double* lms, double* cams_prev, double* lms_prev,
+                             double* part3) {
+    if (!h) return DABA_E_INVAL;
+    try {
+        hipck(hipStreamSynchronize(h->stream), "stream sync");
+        if (cams) download_cams(h, h->b.x_c, cams);
+        if (lms) download_lms(h, h->b.x_l, lms);
+        if (cams_prev) download_cams(h, h->b.xp_c, cams_prev);
+        if (lms_prev) download_lms(h, h->b.xp_l, lms_prev);
+        if (part3) {
+            const int S = h->L.S;
+            std::vector<double> ps((size_t)S * kPS);
+            hipck(hipMemcpy(ps.data(), h->p.ps, 8 * ps.size(), hipMemcpyDeviceToHost), "download");
+            const double s2 = h->L.scale * h->L.scale;
+            for (int a = 0; a < S; ++a) {
+                part3[3 * a + 0] = s2 * ps[(size_t)a * kPS + P_FBAR];
+                part3[3 * a + 1] = s2 * ps[(size_t)a * kPS + P_E];
+                part3[3 * a + 2] = ps[(size_t)a * kPS + P_S];
+            }
+        }
+        return DABA_OK;
+    } catch (const Fail& f) {
+        h->err = f.msg;
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        h->err = "host allocation failed";
+        return DABA_E_NOMEM;
+    }
+}
+
+int daba_part_set_checkpoint(daba_part_handle* h, const double* cams, const double* lms, const double* cams_prev,
+                             const double* lms_prev, const double* part3) {
+    if (!h) return DABA_E_INVAL;
+    try {
+        hipck(hipStreamSynchronize(h->stream), "stream sync");
+        if (cams) upload_cams(h, cams, h->b.x_c);
+        if (lms) upload_lms(h, lms, h->b.x_l);
+        if (cams_prev) upload_cams(h, cams_prev, h->b.xp_c);
+        if (lms_prev) upload_lms(h, lms_prev, h->b.xp_l);
+        if (part3) {
+            const int S = h->L.S;
+            std::vector<double> ps((size_t)S * kPS);
+            hipck(hipMemcpy(ps.data(), h->p.ps, 8 * ps.size(), hipMemcpyDeviceToHost), "download");
+            const double s2 = h->L.scale * h->L.scale;
+            for (int a = 0; a < S; ++a) {
+                for (int c = 0; c < 3; ++c)
+                    if (!std::isfinite(part3[3 * a + c])) fail(DABA_E_INVAL, "part3 has a non-finite entry");
+                if (!(part3[3 * a + 2] >= 1.0)) fail(DABA_E_INVAL, "s^a must be >= 1");
+                ps[(size_t)a * kPS + P_FBAR] = part3[3 * a + 0] / s2;
+                ps[(size_t)a * kPS + P_E] = part3[3 * a + 1] / s2;
+                ps[(size_t)a * kPS + P_S] = part3[3 * a + 2];
+            }
+            hipck(hipMemcpy(h->p.ps, ps.data(), 8 * ps.size(), hipMemcpyHostToDevice), "upload");
+        }
+        return DABA_OK;
+    } catch (const Fail& f) {
+        h->err = f.msg;
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        h->err = "host allocation failed";
+        return DABA_E_NOMEM;
+    }
+}
+
 int daba_part_destroy(daba_part_handle* h) {
     delete h;
     return DABA_OK;

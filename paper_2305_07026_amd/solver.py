@@ -227,6 +227,20 @@ class DabaPartSolver:
                   "daba_part_get_state")
         return dict(cams=c, lms=l, metrics=m)
 
+    def checkpoint(self) -> dict:
+        """x^k, x^(k-1) and per partition (Fbar^a(k-1), E^a(k), s^a(k))."""
+        c, l = np.empty((self.M, 15)), np.empty((self.N, 3))
+        cp, lp, p3 = np.empty((self.M, 15)), np.empty((self.N, 3)), np.empty((self.S, 3))
+        self._chk(B.lib.daba_part_get_checkpoint(self._h, *[_ptr(a, C.c_double) for a in (c, l, cp, lp, p3)]),
+                  "daba_part_get_checkpoint")
+        return dict(cams=c, lms=l, cams_prev=cp, lms_prev=lp, part3=p3)
+
+    def restore(self, ck: dict):
+        """Continue from a checkpoint of a solver of the same problem and options."""
+        arrs = [_np(ck.get(n), np.float64) for n in ("cams", "lms", "cams_prev", "lms_prev", "part3")]
+        self._chk(B.lib.daba_part_set_checkpoint(self._h, *[_ptr(a, C.c_double) for a in arrs]),
+                  "daba_part_set_checkpoint")
+
 
 class DabaObjective(torch.autograd.Function):
     """F(cams, lms, uv) of Problem 1 with the hand-written adjoint of App. D.

@@ -175,3 +175,20 @@ def test_restart_average_weights(small, loss, eta):
     assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
     np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
     assert rel(st["metrics"][:, :3], mo[-1, :, :3]) <= 1e-8
+
+
+def test_checkpoint_and_resume_bitwise(small):
+    """A fresh handle restored from a checkpoint continues exactly like the
+    uninterrupted run."""
+    kw = dict(n_partitions=3, loss="huber")
+    full = P.DabaPartSolver(small, **kw)
+    F_full = full.iterate(8)
+    first = P.DabaPartSolver(small, **kw)
+    F_a = first.iterate(4)
+    ck = first.checkpoint()
+    second = P.DabaPartSolver(small, **kw)
+    second.restore(ck)
+    F_b = second.iterate(4)
+    np.testing.assert_array_equal(np.r_[F_a, F_b], F_full)
+    np.testing.assert_array_equal(second.get_state()["cams"], full.get_state()["cams"])
+    np.testing.assert_array_equal(second.get_state()["metrics"], full.get_state()["metrics"])
