@@ -9,15 +9,14 @@
 //                  and H_cl (9x3) of every exact pair, from the camera's
 //                  observations (camera-major order);
 //   kp_lm_build    one lane per landmark: H_ll (3x3), g_l, the damped inverse
-//                  W = (H_ll + mu diag H_ll)^-1, W g_l, and T = H_cl W per
-//                  exact pair;
+//                  W = (H_ll + mu diag H_ll)^-1 and W g_l;
 //   kp_rhs         one wave per camera: b_c = -g_c + sum H_cl W g_l;
 //   kp_schur       one wave per lower 9x9 block of a partition's reduced
-//                  camera system S = H_cc + mu diag - sum T H_cl^T, summed in
-//                  a fixed order over a pair list built at create;
+//                  camera system S = H_cc + mu diag - sum (H_cl W) H_cl^T,
+//                  summed in a fixed order over a pair list built at create;
 //   kp_chol_*      blocked right-looking Cholesky of every S (64x64 tiles);
 //   kp_trsv        L L^T dc = b per partition;
-//   kp_step        dl = -W g_l - sum T^T dc per landmark; retraction
+//   kp_step        dl = -W (g_l + sum H_cl^T dc) per landmark; retraction
 //                  R Exp(dtheta), t + dt, d + dd, l + dl;
 //   kp_eval + kp_reduce1/2   E^a at the trial point (fixed-order sums over
 //                  chunks of each partition's observations);
@@ -85,7 +84,7 @@ struct PP {
     const int4* chunk;                 // reduction chunks: (kind, partition, begin, end)
     int chunk_base[kMaxS + 1];         // chunks of each partition
     double* partial;                   // one sum per chunk
-    double *vc, *vl, *Hcl, *T;
+    double *vc, *vl, *Hcl;
     double *Hcc, *gc, *W, *Wg;
     double *Smat, *vec;
     double* ps;
@@ -547,7 +546,7 @@ __global__ __launch_bounds__(256) void kp_cam_build(PP p, const double* xc, cons
 // One lane per landmark of an active partition: H_ll, g_l from its
 // observations (exact pairs: rho' J_l^T J_l, rho' J_l^T e; split pairs: eq. Q's
 // 2 w lambda^2 I and 2 w lambda (lambda l - g)), xi I and the prox gradient;
-// then W = (H_ll + mu diag H_ll)^-1, W g_l, and T = H_cl W for exact pairs.
+// then W = (H_ll + mu diag H_ll)^-1 and W g_l.
 template <int LOSS>
 __global__ __launch_bounds__(64) void kp_lm_build(PP p, const double* xc, const double* xl, const double* yc,
                                                   const double* yl) {
@@ -637,17 +636,6 @@ __global__ __launch_bounds__(64) void kp_lm_build(PP p, const double* xc, const 
     for (int kk = 0; kk < 9; ++kk) p.W[(size_t)j * 9 + kk] = Wm[kk];
 #pragma unroll
     for (int r = 0; r < 3; ++r) p.Wg[(size_t)j * kLS + r] = Wm[3 * r] * g[0] + Wm[3 * r + 1] * g[1] + Wm[3 * r + 2] * g[2];
-    for (int k = p.lm_off[j]; k < p.lm_off[j + 1]; ++k) {
-        const int o = p.lm_obs[k];
-        if (!p.ointra[o]) continue;
-        const double* h = p.Hcl + (size_t)o * 27;
-        double* t = p.T + (size_t)o * 27;
-        for (int r = 0; r < 9; ++r) {
-            const double h0 = h[3 * r], h1 = h[3 * r + 1], h2 = h[3 * r + 2];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) t[3 * r + c] = h0 * Wm[c] + h1 * Wm[3 + c] + h2 * Wm[6 + c];
-        }
-    }
 }
 
 // One wave per camera: b_c = -g_c + sum over its exact pairs of H_cl W g_l.
@@ -677,8 +665,9 @@ __global__ __launch_bounds__(64) void kp_rhs(PP p) {
 
 // One wave per lower 9x9 block (q1 >= q2) of a partition's reduced camera
 // system: S = [q1 == q2] (H_cc + mu diag H_cc) - sum over the block's pairs of
-// T(o1) H_cl(o2)^T, the pairs (two exact observations of one landmark by
-// cameras q1 and q2) taken from the pair list.  Lane = (pair slot, row third
+// T(o1) H_cl(o2)^T with T(o1) = H_cl(o1) W formed here, the pairs (two exact
+// observations of one landmark by cameras q1 and q2) taken from the pair
+// list.  Lane = (pair slot, row third
 // g = lane & 3, slot 3 idle): 16 pairs at a time, each lane a 3x9 piece; a
 // butterfly over the slots then sums the pieces in a fixed order.
 __global__ __launch_bounds__(256) void kp_schur(PP p) {
@@ -704,11 +693,20 @@ __global__ __launch_bounds__(256) void kp_schur(PP p) {
         for (int v = 0; v < 9; ++v) acc[u][v] = 0.0;
     if (g < 3) {
         for (int e = e0 + slot; e < e1; e += 16) {
-            const double* t = p.T + (size_t)p.ent[2 * e] * 27 + 9 * g;  // rows 3g .. 3g+2 of T(o1)
+            const int o1 = p.ent[2 * e];
+            const double* h1 = p.Hcl + (size_t)o1 * 27 + 9 * g;          // rows 3g .. 3g+2 of H_cl(o1)
+            const double* W = p.W + (size_t)p.olm[o1] * 9;               // the pair's landmark
             const double* h = p.Hcl + (size_t)p.ent[2 * e + 1] * 27;    // H_cl(o2), 9 x 3
-            double tv[9], hv[27];
+            double tv[9], hv[27], hr[9], wv[9];
 #pragma unroll
-            for (int x = 0; x < 9; ++x) tv[x] = t[x];
+            for (int x = 0; x < 9; ++x) hr[x] = h1[x];
+#pragma unroll
+            for (int x = 0; x < 9; ++x) wv[x] = W[x];
+#pragma unroll
+            for (int u = 0; u < 3; ++u)  // rows 3g .. 3g+2 of T(o1) = H_cl(o1) W
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    tv[3 * u + c] = hr[3 * u] * wv[c] + hr[3 * u + 1] * wv[3 + c] + hr[3 * u + 2] * wv[6 + c];
 #pragma unroll
             for (int x = 0; x < 27; ++x) hv[x] = h[x];
 #pragma unroll
@@ -1104,7 +1102,7 @@ __global__ __launch_bounds__(256) void kp_trsv(PP p) {
 
 // Trial point of every active partition: cameras R Exp(dtheta), t + dt,
 // d + dd from the solved vector; landmarks l + dl with
-// dl = -W g_l - sum over exact pairs of T^T dc.
+// dl = -W g_l - W sum over exact pairs of H_cl^T dc.
 __global__ __launch_bounds__(64) void kp_step(PP p, const double* cc, const double* cl, double* tc, double* tl) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < p.M) {
@@ -1126,23 +1124,24 @@ __global__ __launch_bounds__(64) void kp_step(PP p, const double* cc, const doub
         const int j = t - p.M;
         const int a = part_of(p.pl, p.S, j);
         if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0) return;
-        double d[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d[k] = -p.Wg[(size_t)j * kLS + k];
+        double u[3] = {0.0, 0.0, 0.0};  // sum over exact pairs of H_cl^T dc
         for (int k = p.lm_off[j]; k < p.lm_off[j + 1]; ++k) {
             const int o = p.lm_obs[k];
             if (!p.ointra[o]) continue;
             const int i = p.ocam[o];
             const double* dv = p.vec + p.voff[a] + 9 * (i - p.pc[a]);
-            const double* T = p.T + (size_t)o * 27;
+            const double* H = p.Hcl + (size_t)o * 27;
             for (int r = 0; r < 9; ++r) {
                 const double x = dv[r];
 #pragma unroll
-                for (int kk = 0; kk < 3; ++kk) d[kk] -= T[3 * r + kk] * x;
+                for (int kk = 0; kk < 3; ++kk) u[kk] += H[3 * r + kk] * x;
             }
         }
+        const double* W = p.W + (size_t)j * 9;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) tl[(size_t)j * kLS + k] = cl[(size_t)j * kLS + k] + d[k];
+        for (int k = 0; k < 3; ++k)
+            tl[(size_t)j * kLS + k] = cl[(size_t)j * kLS + k] - p.Wg[(size_t)j * kLS + k] -
+                                      (W[3 * k] * u[0] + W[3 * k + 1] * u[1] + W[3 * k + 2] * u[2]);
     }
 }
 
@@ -1536,7 +1535,6 @@ void carve(const PLayout& L, Carve& c, PP& p, Bufs& b) {
     p.vc = c.take<double>(K);
     p.vl = c.take<double>(K);
     p.Hcl = c.take<double>(27 * K);
-    p.T = c.take<double>(27 * K);
     p.Hcc = c.take<double>(81 * M);
     p.gc = c.take<double>(16 * M);
     p.W = c.take<double>(9 * N);

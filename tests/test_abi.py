@@ -130,8 +130,8 @@ def test_part_workspace_bytes_on_host(prob):
     import ctypes as C
     keep, pr, opt = _part_args(prob)
     n = B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt))
-    # at least the per-observation Hessian blocks (2 x 27 doubles each)
-    assert n >= 2 * 27 * 8 * prob["n_obs"]
+    # at least the per-observation camera-landmark Hessian blocks (27 doubles each)
+    assert n >= 27 * 8 * prob["n_obs"]
     for bad in (dict(precision=1), dict(inner_steps=0), dict(xi=0.0), dict(n_partitions=65)):
         keep, pr, opt = _part_args(prob, **bad)
         assert B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt)) == 0, bad
