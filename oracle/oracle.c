@@ -610,6 +610,33 @@ int orc_create(int64_t M, int64_t N, int64_t K, const int32_t *obs_cam, const in
     return 0;
 }
 
+/* Steps 1-2 of an iteration (Sec. V): the Nesterov scalars of
+ * eq. nesterov_scalar, s^(k+1) = (sqrt(4 s^(k)^2 + 1) + 1) / 2 and
+ * gamma^(k) = (s^(k) - 1) / s^(k+1) (0 without acceleration), per partition;
+ * then the extrapolated point of eq. nesterov_x, with the rotation
+ * projected by eq. proj_rot3d.  s[] is advanced in place. */
+static int nesterov_extrapolate(const orc_state *st, double *s, double *gam, ocam *cbar, double *lbar) {
+    int err = 0;
+    for (int a = 0; a < st->S; ++a) {
+        double snext = (sqrt(4.0 * s[a] * s[a] + 1.0) + 1.0) / 2.0;
+        gam[a] = st->accelerate ? (s[a] - 1.0) / snext : 0.0;
+        s[a] = snext;
+    }
+#pragma omp parallel for schedule(static) reduction(min : err)
+    for (int64_t i = 0; i < st->M; ++i) {
+        double g = gam[st->cpart[i]], Mx[9];
+        for (int a = 0; a < 9; ++a) Mx[a] = st->c[i].R[a] + g * (st->c[i].R[a] - st->cm1[i].R[a]);
+        if (orc_projrot3d(Mx, cbar[i].R)) err = -5;
+        for (int a = 0; a < 3; ++a) cbar[i].t[a] = st->c[i].t[a] + g * (st->c[i].t[a] - st->cm1[i].t[a]);
+        for (int a = 0; a < 3; ++a) cbar[i].d[a] = st->c[i].d[a] + g * (st->c[i].d[a] - st->cm1[i].d[a]);
+    }
+    for (int64_t j = 0; j < st->N; ++j) {
+        double g = gam[st->lpart[j]];
+        for (int a = 0; a < 3; ++a) lbar[3 * j + a] = st->l[3 * j + a] + g * (st->l[3 * j + a] - st->lm1[3 * j + a]);
+    }
+    return err;
+}
+
 int orc_iterate(orc_state *st, int n, double *F_trace, double *metrics_trace) {
     int64_t M = st->M, N = st->N, K = st->K;
     int S = st->S;
@@ -623,26 +650,8 @@ int orc_iterate(orc_state *st, int n, double *F_trace, double *metrics_trace) {
     int *restart = malloc(sizeof(int) * S);
     int err = 0;
     for (int it = 0; it < n && !err; ++it) {
-        /* Nesterov scalars, eq. nesterov_scalar */
-        for (int a = 0; a < S; ++a) {
-            double snext = (sqrt(4.0 * st->s[a] * st->s[a] + 1.0) + 1.0) / 2.0;
-            gam[a] = st->accelerate ? (st->s[a] - 1.0) / snext : 0.0;
-            st->s[a] = snext;
-        }
-        /* extrapolation, eq. nesterov_x */
-#pragma omp parallel for schedule(static) reduction(min : err)
-        for (int64_t i = 0; i < M; ++i) {
-            double g = gam[st->cpart[i]], Mx[9];
-            for (int a = 0; a < 9; ++a) Mx[a] = st->c[i].R[a] + g * (st->c[i].R[a] - st->cm1[i].R[a]);
-            if (orc_projrot3d(Mx, cbar[i].R)) err = -5;
-            for (int a = 0; a < 3; ++a) cbar[i].t[a] = st->c[i].t[a] + g * (st->c[i].t[a] - st->cm1[i].t[a]);
-            for (int a = 0; a < 3; ++a) cbar[i].d[a] = st->c[i].d[a] + g * (st->c[i].d[a] - st->cm1[i].d[a]);
-        }
-        for (int64_t j = 0; j < N; ++j) {
-            double g = gam[st->lpart[j]];
-            for (int a = 0; a < 3; ++a) lbar[3 * j + a] = st->l[3 * j + a] + g * (st->l[3 * j + a] - st->lm1[3 * j + a]);
-        }
-        if (err) break;
+        /* steps 1-2: Nesterov scalars and the extrapolated point */
+        if ((err = nesterov_extrapolate(st, st->s, gam, cbar, lbar))) break;
         /* eq. Fak: F^a(k) = E^a(k) + DeltaE^a(x^k | x^(k-1)) */
         if ((err = linearize(st, st->cm1, st->lm1, lin_prev))) break;
         if ((err = dE_alpha(st, lin_prev, st->cm1, st->lm1, st->c, st->l, dE, Pv, Qv, Fv))) break;
@@ -825,6 +834,21 @@ int orc_grad(orc_state *st, const double *cameras, const double *landmarks, cons
     free(gobs);
     if (uv) free(u);
     free(c); free(l);
+    return err;
+}
+
+int orc_extrapolation(const orc_state *st, double *gamma_out, double *cams_bar, double *lms_bar) {
+    double *s = malloc(sizeof(double) * st->S), *gam = malloc(sizeof(double) * st->S);
+    ocam *cbar = malloc(sizeof(ocam) * (st->M > 0 ? st->M : 1));
+    double *lbar = malloc(sizeof(double) * 3 * (st->N > 0 ? st->N : 1));
+    memcpy(s, st->s, sizeof(double) * st->S);
+    int err = nesterov_extrapolate(st, s, gam, cbar, lbar);
+    if (!err) {
+        if (gamma_out) memcpy(gamma_out, gam, sizeof(double) * st->S);
+        if (cams_bar) for (int64_t i = 0; i < st->M; ++i) cam_to_caller(&cbar[i], st->scale, &cams_bar[15 * i]);
+        if (lms_bar) memcpy(lms_bar, lbar, sizeof(double) * 3 * st->N);
+    }
+    free(s); free(gam); free(cbar); free(lbar);
     return err;
 }
 

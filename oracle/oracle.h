@@ -80,6 +80,12 @@ int orc_set_state(orc_state *st, const double *cams, const double *lms,
                   const double *cams_prev, const double *lms_prev, const double *part4,
                   const double *scalars2);
 
+/* Steps 1-2 of the next iteration without taking it (a probe of Sec. V):
+ * gamma^a(k) per partition [S] (eq. nesterov_scalar) and the extrapolated
+ * point x-bar^(k) of eq. nesterov_x (cameras [M*15] in caller units,
+ * landmarks [N*3]).  The state is not changed.  Any pointer may be NULL. */
+int orc_extrapolation(const orc_state *st, double *gamma_out, double *cams_bar, double *lms_bar);
+
 /* Per-partition E^a(x | y) and DeltaE^a(x | y) (pixels^2) by direct sums;
  * x and y in caller units; out arrays [S]. */
 int orc_surrogate(orc_state *st, const double *cams_x, const double *lms_x,

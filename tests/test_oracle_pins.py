@@ -351,6 +351,99 @@ def test_nesterov_scalars(tiny):
     assert np.allclose(a.get_state()["lms"], b.get_state()["lms"], rtol=0, atol=1e-12)
 
 
+# gamma^(k) for k = 0..3, worked by hand from eq. nesterov_scalar
+# (s^(0) = 1, s^(k) = (sqrt(4 s^(k-1)^2 + 1) + 1) / 2, gamma^(k) = (s^(k) - 1) / s^(k+1)):
+# s = 1, 1.618034, 2.193527, 2.749791, 3.294881 to six places.
+GAMMA_0_3 = (0.0, 0.281754, 0.434043, 0.531064)
+
+
+def test_nesterov_gamma_sequence(tiny):
+    """eq. nesterov_scalar: gamma^(0..3) = 0, 0.281754, 0.434043, 0.531064 on
+    every partition; eq. gamma_bnd: 0 <= gamma^(k) <= (s^(k) - 1) / s^(k) < 1;
+    without acceleration gamma = 0."""
+    o = Oracle(tiny, loss="huber", n_partitions=2)
+    for k, want in enumerate(GAMMA_0_3):
+        g, _, _ = o.extrapolation()
+        assert g.shape == (2,)
+        assert np.all(np.abs(g - want) <= 5e-7), (k, g, want)
+        o.iterate(1)
+    for _ in range(40):
+        g, _, _ = o.extrapolation()
+        s = o.get_state()["s"]
+        assert np.all((g >= 0) & (g <= (s - 1) / s + 1e-15) & (g < 1))
+        o.iterate(1)
+    d = Oracle(tiny, loss="huber", accelerate=False)
+    d.iterate(3)
+    assert np.all(d.extrapolation()[0] == 0.0)
+
+
+def test_nesterov_extrapolation_by_hand(tiny):
+    """eq. nesterov_x with eq. proj_rot3d, computed here from the oracle's
+    x^k and x^(k-1) at k = 3: R-bar = numpy-SVD projection of
+    R + gamma (R - R^(k-1)); t, d and l extrapolated linearly (d in caller
+    units: the unit conversion is linear per component)."""
+    o = Oracle(tiny, loss="huber", n_partitions=2)
+    o.iterate(3)
+    st = o.get_state()
+    g, cb, lb = o.extrapolation()
+    gam = GAMMA_0_3[3]
+    assert np.allclose(g, gam, atol=5e-7)
+    gam = float(g[0])
+    c, cp = st["cams"], st["cams_prev"]
+    # the iterates have moved, so a sign or factor mistake shows
+    assert np.max(np.abs(c[:, :9] - cp[:, :9])) > 1e-5 and np.max(np.abs(st["lms"] - st["lms_prev"])) > 1e-5
+    for i in range(c.shape[0]):
+        R, Rp = c[i, :9].reshape(3, 3), cp[i, :9].reshape(3, 3)
+        assert np.allclose(cb[i, :9], _umeyama_numpy(R + gam * (R - Rp)).ravel(), rtol=0, atol=2e-14)
+        want = c[i, 9:] + gam * (c[i, 9:] - cp[i, 9:])
+        assert np.allclose(cb[i, 9:], want, rtol=1e-14, atol=1e-15)
+    want = st["lms"] + gam * (st["lms"] - st["lms_prev"])
+    assert np.allclose(lb, want, rtol=1e-14, atol=1e-15)
+    # the probe changes nothing: the next iteration is the one without it
+    a = Oracle(tiny, loss="huber", n_partitions=2)
+    a.iterate(3)
+    assert np.array_equal(o.iterate(2)[0], a.iterate(2)[0])
+
+
+# Textbook closed forms with delta = 1 px, at |e| = 0.5, 1 and 3 px:
+# Huber   rho(s) = s (|e| <= delta), 2 delta |e| - delta^2 (above); w = rho'(s) = 1 or delta / |e|;
+# Welsch  rho(s) = delta^2 (1 - exp(-s / delta^2)); w = exp(-s / delta^2).
+LOSS_CLOSED_FORMS = {
+    "huber": {0.5: (0.25, 1.0), 1.0: (1.0, 1.0), 3.0: (5.0, 1.0 / 3.0)},
+    "welsch": {0.5: (0.22119921692859512, 0.7788007830714049),
+               1.0: (0.6321205588285577, 0.36787944117144233),
+               3.0: (0.9998765901959134, 1.2340980408667956e-4)},
+}
+
+
+@pytest.mark.parametrize("unit_scale", [512.0, 1.0])
+@pytest.mark.parametrize("loss", ["huber", "welsch"])
+def test_loss_closed_forms_in_pixels(loss, unit_scale):
+    """Assumption 1 with readings R7 and R9: rho and w of Huber and Welsch
+    at |e| = 0.5, 1 and 3 px for delta = 1 px, through the objective (F in
+    px^2 = sum rho / 2, eq. Fij) and through one observation's evaluation in
+    internal units, at two unit scales (delta becomes delta / s inside).  A
+    camera at the origin looking down +z with f = 500 px sees a point on its
+    axis; the pixel (|e|, 0) then has residual exactly |e| px."""
+    errs = sorted(LOSS_CLOSED_FORMS[loss])
+    prob = dict(n_cameras=1, n_landmarks=len(errs), n_obs=len(errs),
+                obs_camera=np.zeros(len(errs), np.int32), obs_landmark=np.arange(len(errs), dtype=np.int32),
+                obs_uv=np.array([[e, 0.0] for e in errs]),
+                cameras=np.concatenate([np.eye(3).ravel(), np.zeros(3), [500.0, 0.0, 0.0]])[None, :],
+                landmarks=np.tile([0.0, 0.0, 10.0], (len(errs), 1)))
+    o = Oracle(prob, loss=loss, delta=1.0, unit_scale=unit_scale)
+    want_rho = np.array([LOSS_CLOSED_FORMS[loss][e][0] for e in errs])
+    want_w = np.array([LOSS_CLOSED_FORMS[loss][e][1] for e in errs])
+    assert np.isclose(o.objective(), 0.5 * want_rho.sum(), rtol=1e-13, atol=0)
+    ci = o.to_internal(prob["cameras"])[0]
+    for q, e in enumerate(errs):
+        v = o.obs_eval(ci, prob["landmarks"][q], prob["obs_uv"][q] / unit_scale)
+        assert np.isclose(np.sqrt(v["s"]) * unit_scale, e, rtol=1e-14)
+        assert np.isclose(v["rho"] * unit_scale ** 2, want_rho[q], rtol=1e-13, atol=0), (loss, e)
+        assert np.isclose(v["w"], want_w[q], rtol=1e-13, atol=0), (loss, e)
+        assert np.isclose(v["F"] * unit_scale ** 2, 0.5 * want_rho[q], rtol=1e-13, atol=0)
+
+
 def test_mm_monotone_without_acceleration(small):
     """Sec. IV: F(x^{k+1}) <= E(x^{k+1} | x^k) <= E(x^k | x^k) = F(x^k)."""
     o = Oracle(small, loss="huber", accelerate=False, n_partitions=3)
