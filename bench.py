@@ -362,7 +362,8 @@ def main():
                      "frac_of_attainable": achieved / attainable if attainable else None},
         "ms_per_step_repeats": repeats,
         "ms_per_step_median": sorted(repeats)[1],
-        "kernel_ms_per_step": {"k_obs_dma": kern[0], "k_entity": kern[1], "k_decide (+k_finalize once)": kern[2]},
+        "kernel_ms_per_step": {"k_tiles": kern[0], "k_lms": kern[1], "k_entity": kern[2],
+                               "k_decide (+k_finalize once)": kern[3]},
         "wall_s_timed_region": wall,
         "setup_s": setup_s,
         "F_after": F_final,

@@ -139,10 +139,11 @@ int daba_set_state(daba_handle *h, const double *cams, const double *lms, const 
 int daba_get_metrics(daba_handle *h, double *metrics);
 
 /* Timing hook for measurement: runs n_iters iterations and returns, through
- * ms_out (host [3]), the summed GPU time in ms of the observation passes, of
- * the camera and landmark subproblems, and of the restart tests (one small
- * launch per iteration) together with the closing launch that stores the
- * final iterate, measured with HIP events on the handle's stream around each
+ * ms_out (host [4]), the summed GPU time in ms of the camera-tile passes, of
+ * the landmark passes (landmark-side sums and landmark subproblems), of the
+ * camera subproblems, and of the restart tests (one small launch per
+ * iteration) together with the closing launch that stores the final
+ * iterate, measured with HIP events on the handle's stream around each
  * launch.  Synchronizes. */
 int daba_iterate_timed(daba_handle *h, int n_iters, double *ms_out);
 

@@ -34,17 +34,22 @@ struct Layout {
     std::vector<int> group_lm0, group_n, group_deg;
     std::vector<int64_t> group_base;
     std::vector<int> obs_order;                 // internal obs -> caller obs
-    std::vector<int> obs_lm, obs_slot;          // internal obs
+    std::vector<uint32_t> obs_lm;               // internal obs: landmark | partition << kLmBits
+    std::vector<int> obs_slot;                  // internal obs -> landmark-major slot
+    std::vector<int> slot_obs;                  // slot -> internal obs
+    std::vector<uint32_t> slot_cam;             // slot: camera | partition << kCamBits
     std::vector<int> cam_off;                   // [M+1] internal obs offsets
     std::vector<int> tile_cam, tile_begin, tile_end, cam_tile_off;
     std::vector<int> camblock_c0, camblock_c1, part_camblk;
     std::vector<int> lmblock_g0, lmblock_g1, part_lmblk, lmblock_part;
     int T = 0, G = 0;
+    int block_obs = kTileMax;                   // observations per tile at most, per landmark block about
 };
 
-// Landmark-pass blocks of at most `per_block` consecutive groups of one
-// partition (one wave per group).
-void build_lm_blocks(Layout& L, int per_block) {
+// Landmark blocks of the fused pass: consecutive whole groups of one
+// partition, closed once they hold at least `obs_per_block` observations (a
+// group of landmarks nobody observes counts as one); one wave per block.
+void build_lm_blocks(Layout& L, int64_t obs_per_block) {
     L.lmblock_g0.clear();
     L.lmblock_g1.clear();
     L.lmblock_part.clear();
@@ -54,10 +59,17 @@ void build_lm_blocks(Layout& L, int per_block) {
         L.part_lmblk[a] = (int)L.lmblock_g0.size();
         int g0 = g;
         while (g < L.G && L.lpart[L.lm_ext[L.group_lm0[g]]] == a) ++g;
-        for (int q = g0; q < g; q += per_block) {
-            L.lmblock_g0.push_back(q);
-            L.lmblock_g1.push_back(std::min(q + per_block, g));
-            L.lmblock_part.push_back(a);
+        int64_t held = 0;
+        int open = g0;
+        for (int q = g0; q < g; ++q) {
+            held += std::max<int64_t>((int64_t)L.group_n[q] * L.group_deg[q], 1);
+            if (held >= obs_per_block || q + 1 == g) {
+                L.lmblock_g0.push_back(open);
+                L.lmblock_g1.push_back(q + 1);
+                L.lmblock_part.push_back(a);
+                open = q + 1;
+                held = 0;
+            }
         }
     }
     L.part_lmblk[L.S] = (int)L.lmblock_g0.size();
@@ -89,8 +101,9 @@ void hipcheck(hipError_t e, const char* what) {
 void validate_sizes(const daba_problem* p) {
     if (!p) fail(DABA_E_INVAL, "problem is NULL");
     if (p->n_cameras < 1 || p->n_landmarks < 1 || p->n_obs < 0) fail(DABA_E_INVAL, "need M >= 1, N >= 1, K >= 0");
-    if (p->n_cameras > (1 << 30) || p->n_landmarks > kLmMask || p->n_obs > 2000000000LL)
-        fail(DABA_E_INVAL, "problem too large (at most 2^30 cameras, 2^%d - 1 landmarks, 2e9 observations)", kLmBits);
+    if (p->n_cameras > (int64_t)kMaxCameras || p->n_landmarks > (int64_t)kLmMask || p->n_obs > 2000000000LL)
+        fail(DABA_E_INVAL, "problem too large (at most %d cameras, 2^%d - 1 landmarks, 2e9 observations)",
+             kMaxCameras, kLmBits);
     if (p->n_partitions < 1 || p->n_partitions > DABA_MAX_PARTITIONS)
         fail(DABA_E_INVAL, "n_partitions must be in [1, %d]", DABA_MAX_PARTITIONS);
     if (p->n_obs > 0 && (!p->obs_camera || !p->obs_landmark)) fail(DABA_E_INVAL, "observation lists are NULL");
@@ -199,18 +212,30 @@ void build_layout(const daba_problem* p, Layout& L) {
             }
         L.obs_lm.assign(K, 0);
         L.obs_slot.assign(K, 0);
+        L.slot_obs.assign(K, 0);
+        L.slot_cam.assign(K, 0);
         for (int64_t q = 0; q < K; ++q) {
-            int li = L.lm_int[p->obs_landmark[L.obs_order[q]]];
-            int g = gid[li];
-            L.obs_lm[q] = li | (L.lpart[L.lm_ext[li]] << kLmBits);
-            L.obs_slot[q] = (int)(L.group_base[g] + (int64_t)used[li]++ * L.group_n[g] + lane[li]);
+            const int o = L.obs_order[q];
+            const int li = L.lm_int[p->obs_landmark[o]];
+            const int g = gid[li];
+            L.obs_lm[q] = (uint32_t)li | ((uint32_t)L.lpart[L.lm_ext[li]] << kLmBits);
+            const int slot = (int)(L.group_base[g] + (int64_t)used[li]++ * L.group_n[g] + lane[li]);
+            L.obs_slot[q] = slot;
+            L.slot_obs[slot] = (int)q;
+            const int i = p->obs_camera[o];
+            L.slot_cam[slot] = (uint32_t)L.cam_int[i] | ((uint32_t)L.cpart[i] << kCamBits);
         }
     }
-    // tiles: each camera's observations in near-equal pieces of <= kTileMax
+    // tiles: each camera's observations in near-equal pieces of at most
+    // `cap` observations, and landmark blocks of about as many: cap is
+    // K / 4096 rounded up to whole steps, within [kTileMin, kTileMax], so
+    // that a small problem still has a few thousand one-wave blocks
+    const int cap = (int)std::min<int64_t>(kTileMax, std::max<int64_t>(kTileMin, (K / 4096 + kWave - 1) / kWave * kWave));
+    L.block_obs = cap;
     L.cam_tile_off.assign(M + 1, 0);
     for (int64_t ci = 0; ci < M; ++ci) {
         int n = L.cam_off[ci + 1] - L.cam_off[ci];
-        int nt = (n + kTileMax - 1) / kTileMax;
+        int nt = (n + cap - 1) / cap;
         int b = L.cam_off[ci];
         for (int q = 0; q < nt; ++q) {
             int sz = n / nt + (q < n % nt ? 1 : 0);
@@ -232,7 +257,7 @@ void build_layout(const daba_problem* p, Layout& L) {
         }
     }
     L.part_camblk[S] = (int)L.camblock_c0.size();
-    build_lm_blocks(L, kLmWaves);
+    build_lm_blocks(L, cap);
 }
 
 // Workspace carve-up: every array 256-byte aligned.
@@ -252,9 +277,12 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     const size_t M = L.M, N = L.N, K = L.K, S = L.S, T = L.T, G = L.G;
     p.uv = c.take<double2>(K);
     p.uv32 = fp32 ? c.take<float2>(K) : nullptr;
-    p.obs_lm = c.take<int>(K);
-    p.obs_slot = c.take<int>(K);
+    p.obs_lm = c.take<unsigned>(K);
     p.obs_orig = c.take<int>(K);
+    p.luv = c.take<double2>(K);
+    p.luv32 = fp32 ? c.take<float2>(K) : nullptr;
+    p.slot_cam = c.take<unsigned>(K);
+    p.slot_obs = c.take<int>(K);
     p.tile_cam = c.take<int>(T);
     p.tile_begin = c.take<int>(T);
     p.tile_end = c.take<int>(T);
@@ -272,11 +300,17 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.lm_ext = c.take<int>(N);
     p.lm_part = c.take<int>(N);
     for (int g = 0; g < 3; ++g) p.cams[g] = c.take<double>(M * kCamRec);
-    for (int par = 0; par < 2; ++par)
-        for (int q = 0; q < 2; ++q) {
-            p.ccand[par][q] = c.take<double>(M * kCamRec);
-            p.cbar[par][q] = c.take<double>(M * kCamRec);
-        }
+    // the two candidates of a parity are one allocation (the landmark pass
+    // addresses candidate 1 as candidate 0 plus M records), and so are
+    // their extrapolations
+    for (int par = 0; par < 2; ++par) {
+        double* b = c.take<double>(2 * M * kCamRec);
+        p.ccand[par][0] = b;
+        p.ccand[par][1] = b ? b + M * kCamRec : nullptr;
+        double* e = c.take<double>(2 * M * kCamRec);
+        p.cbar[par][0] = e;
+        p.cbar[par][1] = e ? e + M * kCamRec : nullptr;
+    }
     // the two candidates of a parity are one allocation (the observation
     // pass addresses candidate 1 as candidate 0 plus N records)
     for (int par = 0; par < 2; ++par) {
@@ -288,8 +322,6 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
         p.lcp32[par][1] = bf ? bf + N * kLmPair : nullptr;
     }
     p.restart = c.take<int>(S);
-    p.rec = c.take<double>(K * 8);
-    p.rec32 = fp32 ? c.take<float>(K * 8) : nullptr;
     p.tile_vals = c.take<double>(std::max<size_t>(T * kTileVals, 1));
     p.tile_bins = c.take<double>(2 * S * std::max<size_t>(T, 1));
     p.camblk_vals = c.take<double>(L.camblock_c0.size() * 4);
@@ -642,15 +674,24 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
             uv[q] = make_double2(prob->obs_uv[2 * (size_t)o] / p.scale, prob->obs_uv[2 * (size_t)o + 1] / p.scale);
         }
         upload((void*)p.uv, uv.data(), K * sizeof(double2), s);
+        // the same pixels landmark-major, at their slots
+        std::vector<double2> luv(K);
+        for (int64_t q = 0; q < K; ++q) luv[L.obs_slot[q]] = uv[q];
+        upload((void*)p.luv, luv.data(), K * sizeof(double2), s);
         if (fp32) {
-            std::vector<float2> uvf(K);
-            for (int64_t q = 0; q < K; ++q) uvf[q] = make_float2((float)uv[q].x, (float)uv[q].y);
+            std::vector<float2> uvf(K), luvf(K);
+            for (int64_t q = 0; q < K; ++q) {
+                uvf[q] = make_float2((float)uv[q].x, (float)uv[q].y);
+                luvf[L.obs_slot[q]] = uvf[q];
+            }
             upload((void*)p.uv32, uvf.data(), K * sizeof(float2), s);
+            upload((void*)p.luv32, luvf.data(), K * sizeof(float2), s);
             hipcheck(hipStreamSynchronize(s), "sync");
         }
-        upload((void*)p.obs_lm, L.obs_lm.data(), K * sizeof(int), s);
-        upload((void*)p.obs_slot, L.obs_slot.data(), K * sizeof(int), s);
+        upload((void*)p.obs_lm, L.obs_lm.data(), K * sizeof(uint32_t), s);
         upload((void*)p.obs_orig, orig.data(), K * sizeof(int), s);
+        upload((void*)p.slot_cam, L.slot_cam.data(), K * sizeof(uint32_t), s);
+        upload((void*)p.slot_obs, L.slot_obs.data(), K * sizeof(int), s);
         upload((void*)p.tile_cam, L.tile_cam.data(), L.T * sizeof(int), s);
         upload((void*)p.tile_begin, L.tile_begin.data(), L.T * sizeof(int), s);
         upload((void*)p.tile_end, L.tile_end.data(), L.T * sizeof(int), s);
@@ -703,17 +744,20 @@ int daba_create(const daba_problem* prob, const daba_options* opt, void* dev_wor
 }
 
 // One iteration on stream s: the restart test of the previous iteration (one
-// block), the observation pass, the entity solves; ev (optional, 4 events)
-// brackets each launch.
+// block per partition), the camera tiles, the landmark blocks, the camera
+// solves; ev (optional, kEv events) brackets each launch.
+constexpr int kEv = 5;
 static void launch_iteration(daba_handle* h, int k, hipStream_t s, hipEvent_t* ev = nullptr) {
     const Params& p = h->p;
     if (ev) hipcheck(hipEventRecord(ev[0], s), "event");
     hipcheck(launch_decide(p, k, s), "k_decide");
     if (ev) hipcheck(hipEventRecord(ev[1], s), "event");
-    hipcheck(launch_obs_pass(p, k, s), "k_obs");
+    hipcheck(launch_tiles(p, k, s), "k_tiles");
     if (ev) hipcheck(hipEventRecord(ev[2], s), "event");
-    hipcheck(launch_entity(p, k, s), "k_entity");
+    hipcheck(launch_landmarks(p, k, s), "k_lms");
     if (ev) hipcheck(hipEventRecord(ev[3], s), "event");
+    hipcheck(launch_entity(p, k, s), "k_entity");
+    if (ev) hipcheck(hipEventRecord(ev[4], s), "event");
 }
 
 // Captures iterations with k mod 6 = 0..5 once; replaying the graph runs one
@@ -742,25 +786,25 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
     std::vector<hipEvent_t> ev;
     hipEvent_t fin[2] = {nullptr, nullptr};
     int pooled = 0;
-    // ms[0]: observation passes, ms[1]: entity solves, ms[2]: restart tests
-    // (one per iteration) and the closing k_finalize
+    // ms[0]: camera tiles, ms[1]: landmark blocks, ms[2]: camera solves,
+    // ms[3]: restart tests (one per iteration) and the closing k_finalize
     auto drain = [&]() {
         if (pooled == 0) return;
-        hipcheck(hipEventSynchronize(ev[4 * (pooled - 1) + 3]), "event sync");
-        constexpr int slot[3] = {2, 0, 1};
+        hipcheck(hipEventSynchronize(ev[kEv * (pooled - 1) + kEv - 1]), "event sync");
+        constexpr int slot[kEv - 1] = {3, 0, 1, 2};
         for (int q = 0; q < pooled; ++q)
-            for (int e = 0; e < 3; ++e) {
+            for (int e = 0; e < kEv - 1; ++e) {
                 float t = 0.f;
-                hipcheck(hipEventElapsedTime(&t, ev[4 * q + e], ev[4 * q + e + 1]), "elapsed");
+                hipcheck(hipEventElapsedTime(&t, ev[kEv * q + e], ev[kEv * q + e + 1]), "elapsed");
                 ms[slot[e]] += t;
             }
         pooled = 0;
     };
     if (ms) {
-        ev.resize(4 * kPool);
+        ev.resize(kEv * kPool);
         for (auto& e : ev) hipcheck(hipEventCreate(&e), "hipEventCreate");
         for (auto& e : fin) hipcheck(hipEventCreate(&e), "hipEventCreate");
-        for (int e = 0; e < 3; ++e) ms[e] = 0.0;
+        for (int e = 0; e < kEv - 1; ++e) ms[e] = 0.0;
     }
     int done = 0;
     while (done < n) {
@@ -773,7 +817,7 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
                 continue;
             }
             const int k = (int)(h->k % 6);
-            launch_iteration(h, k, s, ms ? &ev[4 * pooled] : nullptr);
+            launch_iteration(h, k, s, ms ? &ev[kEv * pooled] : nullptr);
             if (ms && ++pooled == kPool) drain();
             h->k++;
         }
@@ -785,7 +829,7 @@ static int iterate_impl(daba_handle* h, int n, double* F_trace, double* ms) {
             hipcheck(hipEventSynchronize(fin[1]), "event sync");
             float t = 0.f;
             hipcheck(hipEventElapsedTime(&t, fin[0], fin[1]), "elapsed");
-            ms[2] += t;
+            ms[3] += t;
         }
         if (F_trace) {
             // entries k0+done+1 .. k0+done+chunk-1 were written by this chunk

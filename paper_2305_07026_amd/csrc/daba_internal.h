@@ -4,7 +4,7 @@
 // Device data layout (all inside the caller's workspace):
 //  * observations in camera-major order (internal camera id, then internal
 //    landmark id): pixel uv (double2 / float2, internal units), internal
-//    landmark id, landmark-side slot, original index;
+//    landmark id, original index;
 //  * cameras in partition-major order, one 128-byte record each
 //    (R row-major 9 | t 3 | d 3 | pad): three rotating generations of the
 //    chosen iterate, and the two candidates of the last iteration (plain MM
@@ -15,9 +15,12 @@
 //  * the landmark index of an observation carries its landmark's partition
 //    in the top bits (kLmBits), so a fetch can pick the partition's
 //    candidate without reading the record first;
-//  * landmark-side per-observation records at their slot: groups of up to 64
-//    landmarks with one track length D are stored observation-major
-//    (slot = base + k * n + lane), so the landmark pass reads them coalesced.
+//  * the same observations a second time in landmark-major order, at their
+//    slot: groups of up to 64 landmarks with one track length D are stored
+//    observation-major (slot = base + k * n + lane), and each slot holds the
+//    pixel and the observing camera (partition in the top bits), so the
+//    landmark pass reads them coalesced and gathers only camera records,
+//    which stay in cache.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,16 +31,21 @@ namespace daba {
 
 constexpr int kWave = 64;
 constexpr int kObsWaves = 4;         // waves (tiles) per block of the observation pass
-constexpr int kTileMax = 1024;       // observations per tile (16 per lane)
+constexpr int kTileMax = 1024;       // most observations per tile (16 per lane)
+constexpr int kTileMin = 256;        // fewest observations per tile cap
 constexpr int kMom = 38;             // moments of one surrogate
 constexpr int kTileVals = 80;        // 2 * 38 moments, F share, gap share, pad
 constexpr int kCamRec = 16;          // doubles per camera record
 constexpr int kLmPair = 8;           // doubles per landmark pair record
 constexpr int kCamBlock = 128;       // cameras per block of the camera solve
-constexpr int kLmWaves = 4;          // groups per block of the landmark pass
 constexpr int kMaxPart = 64;
 constexpr int kLmBits = 26;              // landmark index bits in obs_lm (partition above)
-constexpr int kLmMask = (1 << kLmBits) - 1;
+constexpr unsigned kLmMask = (1u << kLmBits) - 1;
+constexpr int kCamBits = 26;             // camera index bits in slot_cam (partition above)
+constexpr unsigned kCamMask = (1u << kCamBits) - 1;
+// the landmark pass addresses a candidate's camera record with a 32-bit
+// byte offset, (candidate M + camera) * 128 < 2^32
+constexpr int kMaxCameras = (1 << 24) - 1;
 
 // Two slots, by iteration parity: the restart test of iteration k - 1 reads
 // slot (k - 1) & 1 and writes slot k & 1, which iteration k then uses.  The
@@ -66,9 +74,13 @@ struct Params {
     // observations (camera-major)
     const double2* uv;
     const float2* uv32;
-    const int* obs_lm;
-    const int* obs_slot;
+    const unsigned* obs_lm;   // internal landmark | partition << kLmBits
     const int* obs_orig;
+    // the observations again, landmark-major at their slots
+    const double2* luv;
+    const float2* luv32;
+    const unsigned* slot_cam; // internal camera | partition << kCamBits
+    const int* slot_obs;      // camera-major index of the slot's observation
     // tiles
     const int* tile_cam;
     const int* tile_begin;
@@ -100,8 +112,6 @@ struct Params {
     double* lcp[2][2];        // [parity][candidate] landmark pair records
     float* lcp32[2][2];
     int* restart;             // [S] restart test of the last decided iteration
-    double* rec;              // [K * 8] landmark-side records at their slots
-    float* rec32;             // [K * 8] the same in FP32 (mixed precision)
     double* tile_vals;        // [T * kTileVals]
     double* tile_bins;        // [2S * T], column q*S + beta
     double* camblk_vals;      // [nCamBlocks * 4]
@@ -128,8 +138,11 @@ static_assert(sizeof(Params) <= 4096, "Params is passed as a kernel argument");
 
 // Launchers (daba_kernels.hip).  k mod 3 selects the camera generation and
 // k mod 2 the landmark pair buffer.
-hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s);
-hipError_t launch_entity(const Params& p, int k, hipStream_t s);  // camera and landmark subproblems
+// Observation pass: camera tiles (moments, F and gap shares), then landmark
+// blocks (landmark-side sums and the landmark subproblems).
+hipError_t launch_tiles(const Params& p, int k, hipStream_t s);
+hipError_t launch_landmarks(const Params& p, int k, hipStream_t s);
+hipError_t launch_entity(const Params& p, int k, hipStream_t s);  // camera subproblems, bin column sums
 // Restart test of iteration k - 1 unless already stored (one block).
 hipError_t launch_decide(const Params& p, int k, hipStream_t s);
 // Restart test of iteration k - 1 and the choice of its candidates, written

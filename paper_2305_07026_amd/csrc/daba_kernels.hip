@@ -4,23 +4,26 @@
 // adaptive restart (Sec. V).
 //
 // Per iteration k (k mod 3 picks the camera generation, k mod 2 the parity
-// of the candidate buffers), three launches:
+// of the candidate buffers), four launches:
 //   k_decide   (one block per partition) the restart test of iteration
 //              k - 1 (eq. Fak, lFak, Eak), which picks each partition's
 //              candidate (eq. update_amm or update_mm) as x^k;
-//   k_obs_dma  one wave per camera tile evaluates every observation at x^k,
-//              taken from that candidate, at the extrapolated
-//              x-bar^k and at x^(k-1); accumulates the camera moments of both
-//              surrogates (FP64), the F share and the surrogate-gap share;
-//              bins the landmark-side shares per partition; writes the
-//              landmark-side record to its slot.
+//   k_tiles    one wave per camera tile: evaluates its camera's
+//              observations at x^k (taken from the chosen candidate), at
+//              the extrapolated x-bar^k and at x^(k-1); accumulates the
+//              camera moments of both surrogates (FP64), the F share and
+//              the surrogate-gap share, and bins the landmark-side shares
+//              per partition;
+//   k_lms      one wave per landmark block walks the same observations
+//              landmark-major, one lane per landmark: the pixel and camera
+//              index of each of its observations read coalesced, the two
+//              cameras gathered (their records stay in cache), the
+//              landmark-side sums of both surrogates formed in registers
+//              and the landmark subproblems solved in closed form;
 //   k_entity   camera subproblems (Levenberg-Marquardt on the moments, and
-//              the next extrapolation of each candidate, eq. nesterov_x) and,
-//              in other blocks of the same launch, the column sums of the
-//              partition bins (the first also sums the objective the restart
-//              test split by partition) and landmark subproblems (one lane
-//              per landmark: the records k_obs_dma wrote at its slots, then
-//              the closed form).
+//              the next extrapolation of each candidate, eq. nesterov_x) and
+//              the column sums of the partition bins (the first also sums
+//              the objective the restart test split by partition).
 // At the end of a call a last k_decide takes the restart test, and
 // k_finalize writes the chosen candidates everywhere, so that between calls
 // x^k is stored plainly.
@@ -224,13 +227,6 @@ __device__ __forceinline__ const float* pair_base<float>(const Params& p, int k,
     return p.lcp32[(k + 1) & 1][cand];
 }
 
-template <typename R>
-__device__ __forceinline__ R* rec_base(const Params& p);
-template <>
-__device__ __forceinline__ double* rec_base<double>(const Params& p) { return p.rec; }
-template <>
-__device__ __forceinline__ float* rec_base<float>(const Params& p) { return p.rec32; }
-
 // Segmented sum over lanes whose keys are sorted (equal keys contiguous);
 // the last lane of each run adds the run's sum into bins[key].
 __device__ __forceinline__ void bin_add_sorted(double v0, double v1, int key, int lane, double* bins0,
@@ -408,44 +404,65 @@ __device__ __forceinline__ uint64_t restart_mask(const Params& p) {
 // candidate chosen for partition a: 0 (plain MM) on restart, else 1
 __device__ __forceinline__ int chosen(uint64_t restart, int a) { return ((restart >> a) & 1) ? 0 : 1; }
 
-// ------------------------------------- observation pass, restructured form
-// The observation pass with its memory traffic restructured for gfx950
-// (FP64, and FP32-mixed with 32-byte records):
-//  * a step's 64 landmark pair records are fetched straight into LDS
-//    (global_load_lds, no VGPRs), several lanes per record (16 bytes each) so
-//    that a wave instruction touches a few cache lines instead of 64; pixels
-//    and slots come the same way.  The fetch for step s + 1 is issued while
-//    step s computes, into the other of two buffers, and the landmark
-//    indices it needs are loaded one step earlier still;
-//  * the landmark-side records of step s are staged in LDS and written at
-//    the start of step s + 1, again several lanes per record.  On this
-//    target a load's wait also waits for every store issued before it, so
-//    stores go out right after a step's wait, a whole step ahead of the next.
-// Every wave waits for all of its vector memory operations at the start of
-// a step, explicitly: the compiler does not order an LDS read after an LDS
-// DMA into the same object.  The two buffers are separate objects, so that
-// reading one while the other is being filled needs no wait.
+// --------------------------------------------- observation pass: camera tiles
+// One camera tile of the fused pass, with its memory traffic arranged for
+// gfx950 (FP64, and FP32-mixed with 32-byte pair records): a step's 64
+// landmark pair records are fetched straight into LDS (global_load_lds, no
+// VGPRs), several lanes per record (16 bytes each) so that a wave
+// instruction touches a few cache lines instead of 64; pixels come the same
+// way.  The fetch for step s + 1 is issued while step s computes, into the
+// other of two buffers, and the landmark indices it needs are loaded one
+// step earlier still.  Every wave waits for its vector memory operations
+// at the start of a step, explicitly: the compiler does not order an LDS
+// read after an LDS DMA into the same object.  The buffers are separate
+// objects, so that reading one while another is being filled needs no
+// wait.  No LDS instruction may run while a DMA is in flight unless it
+// names its object: the compiler would order it after every outstanding
+// DMA (vmcnt(0)), so the landmark indices travel between lanes by DPP.
+// The tile writes nothing per observation: the landmark side of each pair
+// is evaluated again by the landmark blocks.
+//
+// Pair records in LDS: wave instruction i of a fetch brings the records of
+// observations kNI a + i (a = 0 .. kRPI - 1), kLPR lanes per record in order,
+// into the 1 KB at 1040 i, so the record of lane M starts at
+// 1040 (M mod kNI) + kRecB (M / kNI): the 16-byte skew between the slabs
+// makes the lanes' reads of their own records conflict free.
 constexpr int kRedHalf = 7;  // rows of the reduction transpose per buffer (7 x 65 <= 512)
 template <typename R>
 struct ObsBuf;
 template <>
 struct __align__(16) ObsBuf<double> {
-    double pair[kWave * kLmPair];  // pair records of a step, in observation order
+    char pair[1040 * 3 + 1024 + 16];  // pair records of a step (4 slabs)
     double2 uv[kWave];
-    int slot[kWave];
-    __device__ double* red() { return pair; }  // reused for the tile reduction
+    __device__ double* red() { return reinterpret_cast<double*>(pair); }  // reused for the tile reduction
 };
 template <>
 struct __align__(16) ObsBuf<float> {
-    float pair[kWave * kLmPair];
+    char pair[1040 + 1024 + 16];  // 2 slabs
     float ux[kWave], uy[kWave];
-    int slot[kWave];
     double red_[kRedHalf * (kWave + 1)];
     __device__ double* red() { return red_; }
 };
-static_assert(kRedHalf * (kWave + 1) <= kWave * kLmPair, "reduction fits a pair buffer");
+static_assert(kRedHalf * (kWave + 1) * sizeof(double) <= sizeof(ObsBuf<double>::pair), "reduction fits a pair buffer");
+
+// Lane j of the lane's quad (j < 4 a compile-time constant) by DPP, and the
+// lane 2 (q / 2) + j of its pair for FP32 records (two lanes per record).
+template <int J>
+__device__ __forceinline__ int quad_lane(int v) {
+    return __builtin_amdgcn_mov_dpp(v, J | (J << 2) | (J << 4) | (J << 6), 0xF, 0xF, false);
+}
+template <int J>
+__device__ __forceinline__ int pair_lane(int v) {
+    return __builtin_amdgcn_mov_dpp(v, J | (J << 2) | ((2 + J) << 4) | ((2 + J) << 6), 0xF, 0xF, false);
+}
 
 typedef __attribute__((address_space(3))) void* lds_ptr;
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+// the 32-bit LDS address of a __shared__ object
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
 __device__ __forceinline__ void dma16(const void* g, void* l) {
     __builtin_amdgcn_global_load_lds(g, (lds_ptr)l, 16, 0, 0);
 }
@@ -464,21 +481,43 @@ __device__ __forceinline__ void wait_vmem() {
 // One wave per workgroup (one tile each): every LDS address is then a
 // compile-time offset from the lane's own, which keeps VGPRs for the 78
 // FP64 accumulators.
+// LDS of the fused pass (separate objects, so that the compiler can see
+// that a read of one buffer does not depend on a DMA into the other).
+template <typename R>
+struct TileLds {
+    ObsBuf<R>& A;
+    ObsBuf<R>& B;
+    ObsBuf<R>& C;
+    double (&bins)[2][kMaxPart];
+    double* cprev;  // x^(k-1) of the tile's camera (used by the gap only)
+    double* cbarl;  // x-bar^k of the tile's camera
+};
+
+// vmcnt(n) with expcnt and lgkmcnt left alone (gfx9 encoding: vmcnt bits
+// 3:0 and 15:14)
+template <int N>
+__device__ __forceinline__ void wait_vmem_n() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <typename R, int LOSS, bool ACC>
-__global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
-    constexpr int kRecB = 8 * (int)sizeof(R);  // bytes of a pair record and of a landmark-side record
+__device__ __forceinline__ void tile_role(const Params& p, int k, int t, const TileLds<R>& sh) {
+    constexpr int kRecB = 8 * (int)sizeof(R);  // bytes of a pair record
     constexpr int kLPR = kRecB / 16;           // lanes per record
     constexpr int kRPI = kWave / kLPR;         // records per wave instruction
     constexpr int kNI = kWave / kRPI;          // instructions per step
-    constexpr int kEPC = 16 / (int)sizeof(R);  // elements per 16-byte chunk
-    __shared__ ObsBuf<R> A;
-    __shared__ ObsBuf<R> B;
-    __shared__ __align__(16) R stg[kWave * 8];  // landmark-side records of a step
-    __shared__ double bins[2][kMaxPart];
-    __shared__ double cprev[kCamRec];  // x^(k-1) of the tile's camera (used by the gap only)
-    __shared__ double cbarl[kCamRec];  // x-bar^k of the tile's camera
+    // memory instructions of one step's fetch: the pair records, then the pixels
+    constexpr int kNF = kNI + (sizeof(R) == 8 ? 1 : 2);
+    ObsBuf<R>& A = sh.A;
+    ObsBuf<R>& B = sh.B;
+    ObsBuf<R>& C = sh.C;
+    double (&bins)[2][kMaxPart] = sh.bins;
+    double* const cprev = sh.cprev;
+    double* const cbarl = sh.cbarl;
     const int lane = threadIdx.x;
-    const int t = blockIdx.x;
     const bool active = t < p.T;
     const int S = p.S;
 
@@ -512,7 +551,6 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
     // follows candidate 0 after N records
     const char* __restrict__ pbase = reinterpret_cast<const char*>(pair_base<R>(p, k, 0));
     const uint64_t cand_stride = (uint64_t)p.N * kRecB;
-    R* __restrict__ rec = rec_base<R>(p);
     bool bad = false;
     int run_key = -1;
     double run0 = 0.0, run1 = 0.0;
@@ -520,11 +558,14 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
 
     const int last = end - 1;  // tiles are never empty
     const int ns = active ? (end - beg + kWave - 1) / kWave : 0;
-    // landmark index (with its partition in the top bits) of each lane's
-    // observation, one step ahead of the fetch; lane kLPR r + c fetches
-    // chunk c of record kRPI i + r in instruction i
-    int li_ahead = 0;
-    auto load_li = [&](int st) { li_ahead = p.obs_lm[min(beg + kWave * st + lane, last)]; };
+    // Three buffers: step s computes from buffer s mod 3 while the fetches of
+    // steps s + 1 and s + 2 are in flight.  The landmark index (with its
+    // partition in the top bits) of each lane's observation in step s is
+    // loaded into li[s mod 3] at step s - 3, before that step's fetch, so
+    // that a step's wait can leave exactly the newest fetch outstanding.
+    // Lane kLPR r + c fetches chunk c of record kRPI i + r in instruction i.
+    int li0 = 0, li1 = 0, li2 = 0;
+    auto load_li = [&](int st, int& dst) { dst = (int)p.obs_lm[min(beg + kWave * st + lane, last)]; };
     // Lane-derived offsets are recomputed inside each step from a lane index
     // the optimizer cannot see through: hoisted out of the loop they would
     // hold VGPRs for its whole length.
@@ -533,15 +574,29 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
         asm volatile("" : "+v"(l));
         return l;
     };
-    auto fetch = [&](int st, ObsBuf<R>& D) {
-        const int ln = opaque_lane(), rr = ln / kLPR, qc = ln % kLPR;
-#pragma unroll
-        for (int i = 0; i < kNI; ++i) {
-            const unsigned lp = (unsigned)__shfl(li_ahead, kRPI * i + rr);
+    // the landmark index of observation kNI (lane / kLPR) + i: lane i of the
+    // lane's quad (FP64, kNI = kLPR = 4) or of its pair (FP32, kNI = kLPR = 2)
+    auto owner_li = [&](int v, auto ic) -> unsigned {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (sizeof(R) == 8) return (unsigned)quad_lane<i>(v);
+        else return (unsigned)pair_lane<i>(v);
+    };
+    static_assert(kNI == kLPR && (kLPR == 4 || kLPR == 2), "record mapping");
+    auto fetch = [&](int st, ObsBuf<R>& D, int li_st) {
+        const int ln = opaque_lane(), qc = ln % kLPR;
+        auto one = [&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const unsigned lp = owner_li(li_st, ic);
             const unsigned li = lp & kLmMask;
             const uint64_t off = (uint64_t)chosen(restart, (int)(lp >> kLmBits)) * cand_stride +
                                  (uint64_t)li * kRecB + 16u * qc;
-            dma16(pbase + off, &D.pair[kRPI * i * 8]);
+            dma16(pbase + off, D.pair + 1040 * i);
+        };
+        one(std::integral_constant<int, 0>{});
+        one(std::integral_constant<int, 1>{});
+        if constexpr (kNI == 4) {
+            one(std::integral_constant<int, 2>{});
+            one(std::integral_constant<int, 3>{});
         }
         const unsigned o = (unsigned)min(beg + kWave * st + ln, last);
         if constexpr (sizeof(R) == 8) {
@@ -550,30 +605,21 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
             dma4(reinterpret_cast<const char*>(p.uv32) + 8u * o, &D.ux[0]);
             dma4(reinterpret_cast<const char*>(p.uv32) + 8u * o + 4u, &D.uy[0]);
         }
-        dma4(reinterpret_cast<const char*>(p.obs_slot) + 4u * o, &D.slot[0]);
     };
-    // records of step st (staged) to their slots (in D, the buffer of step st)
-    auto store_recs = [&](int st, const ObsBuf<R>& D) {
-        const int ln = opaque_lane(), rr = ln / kLPR, qc = ln % kLPR;
-        const int b0 = beg + kWave * st;
-#pragma unroll
-        for (int i = 0; i < kNI; ++i) {
-            const int r = kRPI * i + rr;
-            if (b0 + r < end) {
-                const float4 v = *reinterpret_cast<const float4*>(&stg[r * 8 + kEPC * qc]);
-                *reinterpret_cast<float4*>(rec + (size_t)D.slot[r] * 8 + kEPC * qc) = v;
-            }
-        }
-    };
-    // step st reads buffer C; the next step's data goes to N
-    auto step = [&](int st, const ObsBuf<R>& C, ObsBuf<R>& N) {
-        wait_vmem();
-        if (st > 0) store_recs(st - 1, N);
+    // step st computes from buffer Cur; step st + 2's data goes to F, with
+    // the landmark indices in liF; step st + 3's indices are loaded into liL
+    // Every step issues the same memory operations, also past the tile's
+    // end (then every lane names the tile's last observation: one cache
+    // line), so that the compiler's wait counts stay exact.
+    auto step = [&](int st, const ObsBuf<R>& Cur, ObsBuf<R>& F, const int& liF, int& liL) {
+        // this step's fetch (issued two steps ago) and the indices of step
+        // st + 2 have arrived; step st + 1's fetch may still be in flight
+        wait_vmem_n<kNF>();
+        load_li(st + 3, liL);
+        // the indices before the fetch, so that the fetch is the newest kNF
+        // operations when the next step waits
         __builtin_amdgcn_sched_barrier(0);
-        if (st + 1 < ns) {
-            fetch(st + 1, N);
-            if (st + 2 < ns) load_li(st + 2);
-        }
+        fetch(st + 2, F, liF);
         __builtin_amdgcn_sched_barrier(0);
         const int ln = opaque_lane();
         const int o = beg + kWave * st + ln;
@@ -583,39 +629,54 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
         if (on) {
             R ux, uy, lk0, lk1, lk2, lp0, lp1, lp2;
             int beta;
-            const R* pr = &C.pair[ln * 8];
+            // The step's own buffer is read in one asm block that waits for its
+            // reads: written as plain loads, the compiler would order them
+            // after every DMA still in flight into the other buffers.
+            const unsigned pr = lds_addr(Cur.pair) + 1040u * (unsigned)(ln % kNI) + (unsigned)(kRecB * (ln / kNI));
             if constexpr (sizeof(R) == 8) {
-                const double2 u2 = C.uv[ln];
-                ux = u2.x;
-                uy = u2.y;
-                const double2 q0 = *reinterpret_cast<const double2*>(pr);
-                const double2 q1 = *reinterpret_cast<const double2*>(pr + 2);
-                const double2 q2 = *reinterpret_cast<const double2*>(pr + 4);
-                lk0 = q0.x; lk1 = q0.y; lk2 = q1.x;
-                beta = (int)__double_as_longlong(q1.y);
-                lp0 = q2.x; lp1 = q2.y; lp2 = pr[6];
+                const unsigned ua = lds_addr(Cur.uv) + 16u * (unsigned)ln;
+                v2d u2, q0, q1, q2;
+                double q3;
+                asm volatile(
+                    "ds_read_b128 %0, %5\n\t"
+                    "ds_read_b128 %1, %6\n\t"
+                    "ds_read_b128 %2, %6 offset:16\n\t"
+                    "ds_read_b128 %3, %6 offset:32\n\t"
+                    "ds_read_b64 %4, %6 offset:48\n\t"
+                    "s_waitcnt lgkmcnt(0)"
+                    : "=&v"(u2), "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3)
+                    : "v"(ua), "v"(pr)
+                    : "memory");
+                ux = u2[0];
+                uy = u2[1];
+                lk0 = q0[0]; lk1 = q0[1]; lk2 = q1[0];
+                beta = (int)__double_as_longlong(q1[1]);
+                lp0 = q2[0]; lp1 = q2[1]; lp2 = q3;
             } else {
-                ux = C.ux[ln];
-                uy = C.uy[ln];
-                const float4 f0 = *reinterpret_cast<const float4*>(pr);
-                const float4 f1 = *reinterpret_cast<const float4*>(pr + 4);
-                lk0 = f0.x; lk1 = f0.y; lk2 = f0.z;
-                beta = __float_as_int(f0.w);
-                lp0 = f1.x; lp1 = f1.y; lp2 = f1.z;
+                const unsigned xa = lds_addr(Cur.ux) + 4u * (unsigned)ln, ya = lds_addr(Cur.uy) + 4u * (unsigned)ln;
+                v4f f0, f1;
+                float fx, fy;
+                asm volatile(
+                    "ds_read_b32 %0, %4\n\t"
+                    "ds_read_b32 %1, %5\n\t"
+                    "ds_read_b128 %2, %6\n\t"
+                    "ds_read_b128 %3, %6 offset:16\n\t"
+                    "s_waitcnt lgkmcnt(0)"
+                    : "=&v"(fx), "=&v"(fy), "=&v"(f0), "=&v"(f1)
+                    : "v"(xa), "v"(ya), "v"(pr)
+                    : "memory");
+                ux = fx;
+                uy = fy;
+                lk0 = f0[0]; lk1 = f0[1]; lk2 = f0[2];
+                beta = __float_as_int(f0[3]);
+                lp0 = f1[0]; lp1 = f1[1]; lp2 = f1[2];
             }
             const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
             const R r6u = r4u * r2u, r8u = r4u * r4u;
-            R* sg = &stg[ln * 8];
             ObsEval<LOSS, R> ek;
             eval_obs<LOSS, R>(ck, lk0, lk1, lk2, ux, uy, r2u, r4u, delta, ek);
             bad |= !(ek.r2 > (R)1e-24);
             add_moments<R>(acc, ek.w, ek.lam, ux, uy, r2u, r4u, r6u, r8u, ek.e);
-            // landmark-side record: W = w lambda^2 and V = w lambda e_w per surrogate
-            const R wl = ek.w * ek.lam;
-            sg[0] = wl * ek.lam;
-            sg[1] = wl * ek.e[0];
-            sg[2] = wl * ek.e[1];
-            sg[3] = wl * ek.e[2];
             // F share: each side of the pair gets half of F_ij = rho / 2
             hF = (double)((R)0.25 * ek.rho);
             key = beta;
@@ -658,13 +719,6 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
                 eval_obs<LOSS, R>(cb, lb0, lb1, lb2, ux, uy, r2u, r4u, delta, eb);
                 bad |= !(eb.r2 > (R)1e-24);
                 add_moments<R>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
-                const R wb = eb.w * eb.lam;
-                sg[4] = wb * eb.lam;
-                sg[5] = wb * eb.e[0];
-                sg[6] = wb * eb.e[1];
-                sg[7] = wb * eb.e[2];
-            } else {
-                sg[4] = sg[5] = sg[6] = sg[7] = (R)0;
             }
         }
         {
@@ -690,16 +744,22 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
     };
 
     if (ns > 0) {
-        load_li(0);
-        fetch(0, A);
-        if (ns > 1) load_li(1);
+        load_li(0, li0);
+        wait_vmem();
+        load_li(1, li1);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(0, A, li0);
+        wait_vmem_n<kNF>();  // li1 has arrived
+        load_li(2, li2);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(1, B, li1);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    for (int st = 0; st < ns; st += 2) {
-        step(st, A, B);
-        if (st + 1 < ns) step(st + 1, B, A);
+    for (int st = 0; st < ns; st += 3) {
+        step(st, A, C, li2, li0);
+        if (st + 1 < ns) step(st + 1, B, A, li0, li1);
+        if (st + 2 < ns) step(st + 2, C, B, li1, li2);
     }
-    wait_vmem();
-    if (ns > 0) store_recs(ns - 1, (ns - 1) & 1 ? B : A);
     flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
     if (bad) p.st[0].err = -5;
 
@@ -743,6 +803,245 @@ __global__ __launch_bounds__(kWave) void k_obs_dma(Params p, int k) {
             p.tile_vals[(size_t)t * kTileVals + 2 * kMom + 1] = -g;
         }
     }
+}
+
+// -------------------------------------------- observation pass: landmarks
+
+// One observation's landmark-side terms of one surrogate (eq. Q): with the
+// pair evaluated at the linearization point, W += w lambda^2 and
+// V += w lambda e_w.  The products are formed in the evaluation type and
+// summed in FP64.
+template <int LOSS, typename R>
+__device__ __forceinline__ void lm_terms(const CamT<R>& c, R l0, R l1, R l2, R ux, R uy, R delta, double& W,
+                                         double* V) {
+    const R r2u = ux * ux + uy * uy, r4u = r2u * r2u;
+    ObsEval<LOSS, R> e;
+    eval_obs<LOSS, R>(c, l0, l1, l2, ux, uy, r2u, r4u, delta, e);
+    const R wl = e.w * e.lam;
+    W += (double)(wl * e.lam);
+    V[0] += (double)(wl * e.e[0]);
+    V[1] += (double)(wl * e.e[1]);
+    V[2] += (double)(wl * e.e[2]);
+}
+
+// The observations of a landmark block, one lane per landmark: slot s of
+// landmark lane holds the pixel and the observing camera (with its
+// partition, which picks the candidate the restart test chose).
+template <typename R>
+struct SlotObs {
+    R ux, uy;
+    unsigned cam;
+};
+template <typename R>
+__device__ __forceinline__ SlotObs<R> read_slot(const Params& p, int64_t s);
+template <>
+__device__ __forceinline__ SlotObs<double> read_slot<double>(const Params& p, int64_t s) {
+    const double2 u = p.luv[s];
+    return {u.x, u.y, p.slot_cam[s]};
+}
+template <>
+__device__ __forceinline__ SlotObs<float> read_slot<float>(const Params& p, int64_t s) {
+    const float2 u = p.luv32[s];
+    return {u.x, u.y, p.slot_cam[s]};
+}
+
+// Camera records of a landmark step in LDS: version 0 is x^k, version 1
+// x-bar^k, kCamSlab bytes apart.  The 64 records of a version (one per lane)
+// arrive by LDS DMA in eight wave instructions, eight lanes per record, each
+// lane of a group loading the next 16 bytes of the record's line, so that
+// the addresser sees in-order runs (one record per 8 lanes) and a wave
+// instruction touches 8 cache lines.  Instruction i brings the records of
+// lanes i, 8 + i, ..., 56 + i into the 1 KB at 1040 i: the record of lane M
+// starts at 1040 (M mod 8) + 128 (M / 8).  The 16-byte skew between the
+// slabs puts chunk j of the records of any 16 consecutive lanes in 16
+// different bank groups, so that every lane reading chunk j of its own
+// record is conflict free, and chunk j is an immediate offset from the
+// lane's base.  `rec` is the lane's camera record index in the candidate
+// pair of allocations (candidate * M + camera); base0 / base1 are the x^k and
+// x-bar^k allocations of the parity.
+constexpr int kCamSlab = 8320;  // 1040 * 7 + 1024, rounded up to 16 bytes
+template <bool ACC>
+__device__ __forceinline__ void dma_cams(const double* __restrict__ base0, const double* __restrict__ base1,
+                                         unsigned rec, char* lds) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const unsigned w = (unsigned)__shfl((int)rec, (lane & ~7) + i);
+        const unsigned off = w * (unsigned)(kCamRec * sizeof(double)) + 16u * (unsigned)(lane & 7);
+        dma16(reinterpret_cast<const char*>(base0) + off, lds + 1040 * i);
+        if constexpr (ACC) dma16(reinterpret_cast<const char*>(base1) + off, lds + kCamSlab + 1040 * i);
+    }
+}
+// Version v of the lane's record from LDS (rb: the lane's record offset).
+template <typename R>
+__device__ __forceinline__ CamT<R> lds_cam(const char* lds, int rb, int v) {
+    double x[16];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const double2 c = *reinterpret_cast<const double2*>(lds + kCamSlab * v + rb + 16 * j);
+        x[2 * j] = c.x;
+        x[2 * j + 1] = c.y;
+    }
+    CamT<R> o;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o.r[a] = (R)x[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.t[a] = (R)x[9 + a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o.d[a] = (R)x[12 + a];
+    return o;
+}
+// lgkmcnt(0) with vmcnt and expcnt left alone: every LDS read of a step has
+// returned before the next step's DMA overwrites the records
+__device__ __forceinline__ void wait_lds() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Candidate pair record (l^(k+1) candidate, partition id, l^k) of iteration k.
+__device__ __forceinline__ void write_cand_pair(const Params& p, int k, int cand, int li, const double* ln,
+                                                double beta_bits, const double* lk) {
+    double2* q = reinterpret_cast<double2*>(p.lcp[k & 1][cand] + (size_t)li * kLmPair);
+    q[0] = make_double2(ln[0], ln[1]);
+    q[1] = make_double2(ln[2], beta_bits);
+    q[2] = make_double2(lk[0], lk[1]);
+    q[3] = make_double2(lk[2], 0.0);
+    if (p.fp32) {
+        float4* f = reinterpret_cast<float4*>(p.lcp32[k & 1][cand] + (size_t)li * kLmPair);
+        f[0] = make_float4((float)ln[0], (float)ln[1], (float)ln[2], __int_as_float((int)__double_as_longlong(beta_bits)));
+        f[1] = make_float4((float)lk[0], (float)lk[1], (float)lk[2], 0.0f);
+    }
+}
+
+// Landmark subproblems of one block of whole groups (one partition, about
+// a tile's worth of observations), one kernel of one-wave blocks: for each
+// group of equal track length D, lane q takes landmark group_lm0 + q and
+// walks its D slots, one per step.  A step brings the 64 observing cameras
+// (x^k and, accelerated, x-bar^k) into LDS together; the pixel and camera
+// index of each slot are loaded two steps ahead, after the step's DMAs, so
+// that the step's wait leaves them in flight.  Each observation is
+// evaluated at x^k and at x-bar^k (the camera's stored extrapolation and
+// l-bar = l^k + gamma (l^k - l^(k-1)), eq. nesterov_x).  The sums run in
+// slot order, which is the camera-major order of the landmark's
+// observations.  Then the closed forms (both candidates) and the block's
+// surrogate changes for the restart test.
+template <typename R, int LOSS, bool ACC>
+__device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* lds) {
+    const int lane = threadIdx.x;
+    const double xi = p.xi;
+    const uint64_t restart = restart_mask(p);
+    const int par = (k + 1) & 1;
+    const int lcc = chosen(restart, uniform_int(p.lmblock_part[lb]));
+    const double* __restrict__ lpb = p.lcp[par][lcc];
+    const double* __restrict__ ckb = p.ccand[par][0];
+    const double* __restrict__ cbb = p.cbar[par][0];
+    const unsigned M = (unsigned)p.M;
+    const double gam = ACC ? p.st[k & 1].gamma : 0.0;
+    const R gamr = (R)gam;
+    const R delta = (R)p.delta;
+    // where this lane's camera records sit in LDS
+    const int rb = 1040 * (lane & 7) + 128 * (lane >> 3);
+    const int g0 = uniform_int(p.lmblock_g0[lb]), g1 = uniform_int(p.lmblock_g1[lb]);
+    double dmm = 0.0, dacc = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const int n = uniform_int(p.group_n[g]), D = uniform_int(p.group_deg[g]);
+        const bool on = lane < n;
+        const int ln = on ? lane : 0;  // lanes past n read lane 0's data and discard it
+        const int li = uniform_int(p.group_lm0[g]) + ln;
+        const int64_t base = p.group_base[g] + ln;
+        const LmRead<double> L = read_pair(lpb, li);
+        // the evaluation points in the evaluation type (as the camera tiles
+        // form them from the pair records)
+        const R lk0 = (R)L.lk[0], lk1 = (R)L.lk[1], lk2 = (R)L.lk[2];
+        const R lp0 = (R)L.lp[0], lp1 = (R)L.lp[1], lp2 = (R)L.lp[2];
+        const R lb0 = lk0 + gamr * (lk0 - lp0), lb1 = lk1 + gamr * (lk1 - lp1), lb2 = lk2 + gamr * (lk2 - lp2);
+        double W0 = 0.0, V0[3] = {0.0, 0.0, 0.0}, W1 = 0.0, V1[3] = {0.0, 0.0, 0.0};
+        // slot q of this lane's landmark at base + q n
+        // Slot q + 1 is in s1 and slot q + 2 is loaded during step q; every
+        // step issues the same loads (the prefetch past the last slot
+        // re-reads it), so that the compiler's wait counts stay exact.
+        auto slot_at = [&](int q) { return base + (int64_t)min(q, D - 1) * n; };
+        SlotObs<R> s0{}, s1{};
+        if (D > 0) {
+            s0 = read_slot<R>(p, slot_at(0));
+            s1 = read_slot<R>(p, slot_at(1));
+        }
+        for (int q = 0; q < D; ++q) {
+            const SlotObs<R> cur = s0;
+            // the record of the candidate the camera's partition chose
+            const unsigned rec = (unsigned)chosen(restart, (int)(cur.cam >> kCamBits)) * M + (cur.cam & kCamMask);
+            dma_cams<ACC>(ckb, cbb, rec, lds);
+            // the prefetch must be issued after every DMA, for the count below
+            __builtin_amdgcn_sched_barrier(0);
+            s0 = s1;
+            s1 = read_slot<R>(p, slot_at(q + 2));
+            wait_vmem_n<2>();  // the DMAs; the two loads of slot q + 2 stay in flight
+            if (on) {
+                lm_terms<LOSS, R>(lds_cam<R>(lds, rb, 0), lk0, lk1, lk2, cur.ux, cur.uy, delta, W0, V0);
+                if constexpr (ACC)
+                    lm_terms<LOSS, R>(lds_cam<R>(lds, rb, 1), lb0, lb1, lb2, cur.ux, cur.uy, delta, W1, V1);
+            }
+            wait_lds();
+        }
+        if (!on) continue;
+        // closed forms: l = l^y + V / (2W + xi) about each linearization point
+        double dl[3], nm = 0.0, dv = 0.0;
+        const double den0 = 2.0 * W0 + xi;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dl[a] = V0[a] / den0;
+            nm += dl[a] * dl[a];
+            dv += dl[a] * V0[a];
+        }
+        dmm += (W0 + 0.5 * xi) * nm - dv;
+        const double beta_bits = __longlong_as_double((long long)L.beta);
+        const double lm[3] = {L.lk[0] + dl[0], L.lk[1] + dl[1], L.lk[2] + dl[2]};
+        write_cand_pair(p, k, 0, li, lm, beta_bits, L.lk);
+        if constexpr (ACC) {
+            const double den1 = 2.0 * W1 + xi;
+            double la[3], na = 0.0, va = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
+                la[a] = lbar + V1[a] / den1;
+                const double da = la[a] - L.lk[a];
+                na += da * da;
+                va += da * V0[a];
+            }
+            // the accelerated candidate measured on the surrogate about x^k
+            dacc += (W0 + 0.5 * xi) * na - va;
+            write_cand_pair(p, k, 1, li, la, beta_bits, L.lk);
+        }
+    }
+    dmm = wave_sum(dmm);
+    dacc = wave_sum(dacc);
+    if (lane == 0) {
+        p.lmblk_vals[(size_t)lb * 2] = dmm;
+        p.lmblk_vals[(size_t)lb * 2 + 1] = dacc;
+    }
+}
+
+// The observation pass, two kernels of one-wave blocks on the same stream:
+// camera tiles, then landmark blocks.  Each is bound by the memory requests
+// it keeps in flight (random pair gathers from HBM; camera gathers from
+// cache), so each gets the LDS and registers that maximize that.
+template <typename R, int LOSS, bool ACC>
+__global__ __launch_bounds__(kWave) void k_tiles(Params p, int k) {
+    __shared__ ObsBuf<R> A;
+    __shared__ ObsBuf<R> B;
+    __shared__ ObsBuf<R> C;
+    __shared__ double bins[2][kMaxPart];
+    __shared__ double cprev[kCamRec];
+    __shared__ double cbarl[kCamRec];
+    const TileLds<R> sh{A, B, C, bins, cprev, cbarl};
+    tile_role<R, LOSS, ACC>(p, k, blockIdx.x, sh);
+}
+
+template <typename R, int LOSS, bool ACC>
+__global__ __launch_bounds__(kWave) void k_lms(Params p, int k) {
+    __shared__ __align__(16) char cams[(ACC ? 2 : 1) * kCamSlab];
+    lm_role<R, LOSS, ACC>(p, k, blockIdx.x, cams);
 }
 
 // ---------------------------------------------------- camera subproblem
@@ -1158,126 +1457,12 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, CamLd
     }
 }
 
-// Sums a landmark's records (slots base + q n + lane, q < D), eight in flight
-// per lane; FP32 records are accumulated in FP64.
-template <typename RT, bool ACC>
-__device__ __forceinline__ void sum_records(const RT* __restrict__ rec, int64_t base, int n, int lane, int D,
-                                            double& W0, double* V0, double& W1, double* V1) {
-    using V4 = typename std::conditional<std::is_same<RT, double>::value, double4, float4>::type;
-    constexpr int U = 8;  // the camera role already sets this kernel's VGPR budget
-    for (int q0 = 0; q0 < D; q0 += U) {
-        V4 ra[U], rb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (q0 + u < D) {
-                const V4* r = reinterpret_cast<const V4*>(rec + (size_t)(base + (int64_t)(q0 + u) * n + lane) * 8);
-                ra[u] = r[0];
-                if (ACC) rb[u] = r[1];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (q0 + u < D) {
-                W0 += ra[u].x;
-                V0[0] += ra[u].y;
-                V0[1] += ra[u].z;
-                V0[2] += ra[u].w;
-                if (ACC) {
-                    W1 += rb[u].x;
-                    V1[0] += rb[u].y;
-                    V1[1] += rb[u].z;
-                    V1[2] += rb[u].w;
-                }
-            }
-        }
-    }
-}
-
-// Candidate pair record (l^(k+1) candidate, partition id, l^k) of iteration k.
-__device__ __forceinline__ void write_cand_pair(const Params& p, int k, int cand, int li, const double* ln,
-                                                double beta_bits, const double* lk) {
-    double2* q = reinterpret_cast<double2*>(p.lcp[k & 1][cand] + (size_t)li * kLmPair);
-    q[0] = make_double2(ln[0], ln[1]);
-    q[1] = make_double2(ln[2], beta_bits);
-    q[2] = make_double2(lk[0], lk[1]);
-    q[3] = make_double2(lk[2], 0.0);
-    if (p.fp32) {
-        float4* f = reinterpret_cast<float4*>(p.lcp32[k & 1][cand] + (size_t)li * kLmPair);
-        f[0] = make_float4((float)ln[0], (float)ln[1], (float)ln[2], __int_as_float((int)__double_as_longlong(beta_bits)));
-        f[1] = make_float4((float)lk[0], (float)lk[1], (float)lk[2], 0.0f);
-    }
-}
-
-// Landmark subproblems of one block: one wave per group of equal track
-// length, one lane per landmark (the records it reads are consecutive
-// across the wave's lanes).
-template <typename RT, bool ACC>
-__device__ __forceinline__ void landmark_role(const Params& p, int k, int lb, double (*sred)[4]) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const double xi = p.xi;
-    const int g = p.lmblock_g0[lb] + wv;
-    // l^k and l^(k-1): the candidate of iteration k - 1 chosen for this
-    // block's partition
-    const int lcc = p.restart[p.lmblock_part[lb]] ? 0 : 1;
-    double dmm = 0.0, dacc = 0.0;
-    if (g < p.lmblock_g1[lb]) {
-        const int n = p.group_n[g], D = p.group_deg[g];
-        const int li = p.group_lm0[g] + lane;
-        const int64_t base = p.group_base[g];
-        if (lane < n) {
-            double W0 = 0, V0[3] = {0, 0, 0}, W1 = 0, V1[3] = {0, 0, 0};
-            sum_records<RT, ACC>(rec_base<RT>(p), base, n, lane, D, W0, V0, W1, V1);
-            const LmRead<double> L = read_pair(p.lcp[(k + 1) & 1][lcc], li);
-            double dl[3], nm = 0.0, dv = 0.0;
-            const double den0 = 2.0 * W0 + xi;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                dl[a] = V0[a] / den0;
-                nm += dl[a] * dl[a];
-                dv += dl[a] * V0[a];
-            }
-            dmm = (W0 + 0.5 * xi) * nm - dv;
-            const double beta_bits = __longlong_as_double((long long)L.beta);
-            const double lm[3] = {L.lk[0] + dl[0], L.lk[1] + dl[1], L.lk[2] + dl[2]};
-            write_cand_pair(p, k, 0, li, lm, beta_bits, L.lk);
-            if (ACC) {
-                const double gam = p.st[k & 1].gamma;
-                const double den1 = 2.0 * W1 + xi;
-                double la[3], na = 0.0, va = 0.0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
-                    la[a] = lbar + V1[a] / den1;
-                    const double da = la[a] - L.lk[a];
-                    na += da * da;
-                    va += da * V0[a];
-                }
-                dacc = (W0 + 0.5 * xi) * na - va;
-                write_cand_pair(p, k, 1, li, la, beta_bits, L.lk);
-            }
-        }
-    }
-    dmm = wave_sum(dmm);
-    dacc = wave_sum(dacc);
-    if (lane == 0) {
-        sred[wv][0] = dmm;
-        sred[wv][1] = dacc;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        double s = 0.0;
-        for (int w = 0; w < 4; ++w) s += sred[w][threadIdx.x];
-        p.lmblk_vals[(size_t)lb * 2 + threadIdx.x] = s;
-    }
-}
-
-// One launch, three kinds of blocks: camera subproblems, column sums of the
-// per-tile partition bins, and landmark subproblems (in that order, so that
-// the short column sums are not queued behind the landmark blocks).  The
-// roles are independent, so the camera solves (long serial chains on few
-// threads) overlap the landmark pass.
-template <typename RT, bool ACC>
+// One launch, two kinds of blocks: camera subproblems, then the column sums
+// of the per-tile partition bins (the first of which also stores F of the
+// previous iterate and clears the decided flag).  It runs after the fused
+// pass, which has solved the landmark subproblems, so the camera role's
+// register use (the LM solve) sets only this launch's occupancy.
+template <bool ACC>
 __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
     __shared__ CamLds sh;
     __shared__ double sred[4][4];  // block reductions
@@ -1289,22 +1474,19 @@ __global__ __launch_bounds__(256) void k_entity(Params p, int k) {
         return;
     }
     const int cb = blockIdx.x - p.nCamBlocks;
-    if (cb < 2 * p.S) {
-        // column sums of the per-tile partition bins
-        const double* src = p.tile_bins + (size_t)cb * p.T;
-        double s = 0.0;
-        for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
-        s = wave_sum(s);
-        if (lane == 0) sred[wv][0] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) p.colsum[cb] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
-        // F(x^(k-1)) from the shares this iteration's restart test stored
-        if (cb == 0) store_trace(p, k, fshl);
-        return;
+    // column sums of the per-tile partition bins
+    const double* src = p.tile_bins + (size_t)cb * p.T;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < p.T; t += 256) s += src[t];
+    s = wave_sum(s);
+    if (lane == 0) sred[wv][0] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) p.colsum[cb] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+    // F(x^(k-1)) from the shares this iteration's restart test stored
+    if (cb == 0) {
+        store_trace(p, k, fshl);
+        if (threadIdx.x == 0) p.st[0].decided = 0;
     }
-    const int lb = cb - 2 * p.S;
-    if (lb == 0 && threadIdx.x == 0) p.st[0].decided = 0;
-    landmark_role<RT, ACC>(p, k, lb, sred);
 }
 
 // ------------------------------------------------------- select and roll
@@ -1516,8 +1698,8 @@ __global__ __launch_bounds__(256) void k_import(Params p, const double* __restri
 
 // App. D, eq. DFij: per observation grad_R = -w lambda m e^T (camera-frame e),
 // grad_t = w lambda R e, grad_l = -w lambda R e, grad_d = w e_z (1, |u|^2, |u|^4),
-// grad_u = w (e_xy + e_z (2 d2 + 4 d3 |u|^2) u); camera sums per tile, landmark
-// parts to the observation's slot, pixel parts to the caller's index.
+// grad_u = w (e_xy + e_z (2 d2 + 4 d3 |u|^2) u); camera sums per tile, pixel
+// parts to the caller's index (the landmark parts: k_grad_lms).
 template <typename R, int LOSS>
 __global__ __launch_bounds__(kObsWaves* kWave) void k_grad_obs(Params p, const double* __restrict__ cams,
                                                                const double* __restrict__ lpair,
@@ -1569,10 +1751,6 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_grad_obs(Params p, const d
             acc[12] += (double)(e.w * ec[2]);
             acc[13] += (double)(e.w * ec[2] * r2u);
             acc[14] += (double)(e.w * ec[2] * r2u * r2u);
-            double* lr = p.rec + (size_t)p.obs_slot[o] * 8;
-            lr[0] = (double)(-wl * Re[0]);
-            lr[1] = (double)(-wl * Re[1]);
-            lr[2] = (double)(-wl * Re[2]);
             if (g_uv) {
                 const R dz = (R)2 * c.d[1] + (R)4 * c.d[2] * r2u;
                 const int oi = p.obs_orig[o];
@@ -1593,11 +1771,10 @@ __global__ __launch_bounds__(kObsWaves* kWave) void k_grad_obs(Params p, const d
     }
 }
 
-__global__ __launch_bounds__(256) void k_grad_entities(Params p, double* __restrict__ g_cams,
-                                                       double* __restrict__ g_lms) {
+__global__ __launch_bounds__(256) void k_grad_entities(Params p, double* __restrict__ g_cams) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const double sc = p.scale, s2 = sc * sc;
-    if (i < p.M && g_cams) {
+    if (i < p.M) {
         double acc[15];
 #pragma unroll
         for (int a = 0; a < 15; ++a) acc[a] = 0.0;
@@ -1610,31 +1787,50 @@ __global__ __launch_bounds__(256) void k_grad_entities(Params p, double* __restr
         g[13] = s2 * acc[13] * sc;
         g[14] = s2 * acc[14] * sc * sc * sc;
     }
-    const int64_t j = i - p.M;
-    if (j >= 0 && j < p.N && g_lms) {
-        // landmark li = j: its slots are in its group
-        const int li = (int)j;
-        // find the group by the per-landmark table packed in group arrays:
-        // groups are contiguous in landmark id; binary search
-        int lo = 0, hi = p.G - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (p.group_lm0[mid] <= li) lo = mid;
-            else hi = mid - 1;
-        }
-        const int g = lo, n = p.group_n[g], D = p.group_deg[g], lane = li - p.group_lm0[g];
-        double a0 = 0, a1 = 0, a2 = 0;
-        for (int q = 0; q < D; ++q) {
-            const double* r = p.rec + (size_t)(p.group_base[g] + (int64_t)q * n + lane) * 8;
-            a0 += r[0];
-            a1 += r[1];
-            a2 += r[2];
-        }
-        double* gl = g_lms + (size_t)p.lm_ext[li] * 3;
-        gl[0] = s2 * a0;
-        gl[1] = s2 * a1;
-        gl[2] = s2 * a2;
+}
+
+// Landmark parts of eq. DFij, grad_l = -w lambda R e (camera-frame e), one
+// lane per landmark over its slots (camera-major order of its observations);
+// each slot names the observation, whose pixel comes from uv.
+template <typename R, int LOSS>
+__global__ __launch_bounds__(256) void k_grad_lms(Params p, const double* __restrict__ cams,
+                                                  const double* __restrict__ lpair, const double2* __restrict__ uv,
+                                                  double* __restrict__ g_lms) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= p.N) return;
+    const int li = (int)j;
+    // the landmark's group: groups are contiguous in landmark id
+    int lo = 0, hi = p.G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.group_lm0[mid] <= li) lo = mid;
+        else hi = mid - 1;
     }
+    const int g = lo, n = p.group_n[g], D = p.group_deg[g], lane = li - p.group_lm0[g];
+    const LmRead<double> L = read_pair(lpair, li);
+    const R delta = (R)p.delta;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int q = 0; q < D; ++q) {
+        const int64_t s = p.group_base[g] + (int64_t)q * n + lane;
+        const double2 u2 = uv[p.slot_obs[s]];
+        const CamT<R> c = load_cam<R>(cams + (size_t)(p.slot_cam[s] & kCamMask) * kCamRec);
+        const R ux = (R)u2.x, uy = (R)u2.y;
+        const R r2u = ux * ux + uy * uy;
+        ObsEvalCF<LOSS, R> e;
+        eval_obs_cf<LOSS, R>(c, (R)L.lk[0], (R)L.lk[1], (R)L.lk[2], ux, uy, r2u, r2u * r2u, delta, e);
+        const R wl = e.w * e.lam;
+        R Re[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Re[a] = c.r[3 * a] * e.e[0] + c.r[3 * a + 1] * e.e[1] + c.r[3 * a + 2] * e.e[2];
+        a0 += (double)(-wl * Re[0]);
+        a1 += (double)(-wl * Re[1]);
+        a2 += (double)(-wl * Re[2]);
+    }
+    const double s2 = p.scale * p.scale;
+    double* gl = g_lms + (size_t)p.lm_ext[li] * 3;
+    gl[0] = s2 * a0;
+    gl[1] = s2 * a1;
+    gl[2] = s2 * a2;
 }
 
 // -------------------------------------------------------------- launchers
@@ -1646,31 +1842,39 @@ __global__ __launch_bounds__(256) void k_grad_entities(Params p, double* __restr
     default: { constexpr int LS = 0; BODY; } break; \
     }
 
-hipError_t launch_obs_pass(const Params& p, int k, hipStream_t s) {
+hipError_t launch_tiles(const Params& p, int k, hipStream_t s) {
     if (p.T == 0) return hipSuccess;
-    const int T1 = p.T;
-    dim3 grid((T1 + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
+    const dim3 grid(p.T), block(kWave);
     DABA_LOSS_SWITCH(p.loss, {
         if (p.fp32) {
-            if (p.accelerate) hipLaunchKernelGGL((k_obs_dma<float, LS, true>), dim3(T1), dim3(kWave), 0, s, p, k);
-            else hipLaunchKernelGGL((k_obs_dma<float, LS, false>), dim3(T1), dim3(kWave), 0, s, p, k);
+            if (p.accelerate) hipLaunchKernelGGL((k_tiles<float, LS, true>), grid, block, 0, s, p, k);
+            else hipLaunchKernelGGL((k_tiles<float, LS, false>), grid, block, 0, s, p, k);
         } else {
-            if (p.accelerate) hipLaunchKernelGGL((k_obs_dma<double, LS, true>), dim3(T1), dim3(kWave), 0, s, p, k);
-            else hipLaunchKernelGGL((k_obs_dma<double, LS, false>), dim3(T1), dim3(kWave), 0, s, p, k);
+            if (p.accelerate) hipLaunchKernelGGL((k_tiles<double, LS, true>), grid, block, 0, s, p, k);
+            else hipLaunchKernelGGL((k_tiles<double, LS, false>), grid, block, 0, s, p, k);
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_landmarks(const Params& p, int k, hipStream_t s) {
+    const dim3 grid(p.nLmBlocks), block(kWave);
+    DABA_LOSS_SWITCH(p.loss, {
+        if (p.fp32) {
+            if (p.accelerate) hipLaunchKernelGGL((k_lms<float, LS, true>), grid, block, 0, s, p, k);
+            else hipLaunchKernelGGL((k_lms<float, LS, false>), grid, block, 0, s, p, k);
+        } else {
+            if (p.accelerate) hipLaunchKernelGGL((k_lms<double, LS, true>), grid, block, 0, s, p, k);
+            else hipLaunchKernelGGL((k_lms<double, LS, false>), grid, block, 0, s, p, k);
         }
     });
     return hipGetLastError();
 }
 
 hipError_t launch_entity(const Params& p, int k, hipStream_t s) {
-    dim3 grid(p.nCamBlocks + p.nLmBlocks + 2 * p.S), block(256);
-    if (p.fp32) {
-        if (p.accelerate) hipLaunchKernelGGL((k_entity<float, true>), grid, block, 0, s, p, k);
-        else hipLaunchKernelGGL((k_entity<float, false>), grid, block, 0, s, p, k);
-    } else {
-        if (p.accelerate) hipLaunchKernelGGL((k_entity<double, true>), grid, block, 0, s, p, k);
-        else hipLaunchKernelGGL((k_entity<double, false>), grid, block, 0, s, p, k);
-    }
+    dim3 grid(p.nCamBlocks + 2 * p.S), block(256);
+    if (p.accelerate) hipLaunchKernelGGL((k_entity<true>), grid, block, 0, s, p, k);
+    else hipLaunchKernelGGL((k_entity<false>), grid, block, 0, s, p, k);
     return hipGetLastError();
 }
 
@@ -1717,15 +1921,22 @@ hipError_t launch_import_point(const Params& p, const double* cams, const double
 
 hipError_t launch_grad(const Params& p, const double* cams, const double* lpair, const double2* uv,
                        double* g_cams, double* g_lms, double* g_uv, hipStream_t s) {
-    if (p.T > 0) {
+    if (p.T > 0 && (g_cams || g_uv)) {
         dim3 grid((p.T + kObsWaves - 1) / kObsWaves), block(kObsWaves * kWave);
         DABA_LOSS_SWITCH(p.loss, {
             if (p.fp32) hipLaunchKernelGGL((k_grad_obs<float, LS>), grid, block, 0, s, p, cams, lpair, uv, g_uv);
             else hipLaunchKernelGGL((k_grad_obs<double, LS>), grid, block, 0, s, p, cams, lpair, uv, g_uv);
         });
     }
-    const int64_t n = p.M + p.N;
-    hipLaunchKernelGGL(k_grad_entities, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g_cams, g_lms);
+    if (g_cams)
+        hipLaunchKernelGGL(k_grad_entities, dim3((unsigned)((p.M + 255) / 256)), dim3(256), 0, s, p, g_cams);
+    if (g_lms) {
+        const dim3 grid((unsigned)((p.N + 255) / 256)), block(256);
+        DABA_LOSS_SWITCH(p.loss, {
+            if (p.fp32) hipLaunchKernelGGL((k_grad_lms<float, LS>), grid, block, 0, s, p, cams, lpair, uv, g_lms);
+            else hipLaunchKernelGGL((k_grad_lms<double, LS>), grid, block, 0, s, p, cams, lpair, uv, g_lms);
+        });
+    }
     return hipGetLastError();
 }
 

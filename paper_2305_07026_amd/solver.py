@@ -105,9 +105,10 @@ class DabaSolver:
         return None
 
     def iterate_timed(self, n: int):
-        """n iterations; returns summed GPU ms of (observation passes, entity
-        solves, restart tests and the closing store of the iterate)."""
-        ms = np.zeros(3)
+        """n iterations; returns summed GPU ms of (camera tiles, landmark
+        passes, camera solves, restart tests and the closing store of the
+        iterate)."""
+        ms = np.zeros(4)
         self._chk(B.lib.daba_iterate_timed(self._h, n, _ptr(ms, C.c_double)), "daba_iterate_timed")
         return ms
 
