@@ -43,7 +43,7 @@ struct Layout {
     std::vector<int> camblock_c0, camblock_c1, part_camblk;
     std::vector<int> lmblock_g0, lmblock_g1, part_lmblk, lmblock_part;
     int T = 0, G = 0;
-    int block_obs = kTileMax;                   // observations per tile at most, per landmark block about
+    int block_obs = kTileMax;                   // observations per landmark block, about
 };
 
 // Landmark blocks of the fused pass: consecutive whole groups of one
@@ -227,11 +227,11 @@ void build_layout(const daba_problem* p, Layout& L) {
         }
     }
     // tiles: each camera's observations in near-equal pieces of at most
-    // `cap` observations, and landmark blocks of about as many: cap is
-    // K / 4096 rounded up to whole steps, within [kTileMin, kTileMax], so
-    // that a small problem still has a few thousand one-wave blocks
-    const int cap = (int)std::min<int64_t>(kTileMax, std::max<int64_t>(kTileMin, (K / 4096 + kWave - 1) / kWave * kWave));
-    L.block_obs = cap;
+    // kTileMax observations.  Landmark blocks hold about K / 4096
+    // observations, rounded up to whole steps, within [kTileMin, kTileMax],
+    // so that a small problem still has a few thousand landmark blocks.
+    const int cap = kTileMax;
+    L.block_obs = (int)std::min<int64_t>(kTileMax, std::max<int64_t>(kTileMin, (K / 4096 + kWave - 1) / kWave * kWave));
     L.cam_tile_off.assign(M + 1, 0);
     for (int64_t ci = 0; ci < M; ++ci) {
         int n = L.cam_off[ci + 1] - L.cam_off[ci];
@@ -257,7 +257,7 @@ void build_layout(const daba_problem* p, Layout& L) {
         }
     }
     L.part_camblk[S] = (int)L.camblock_c0.size();
-    build_lm_blocks(L, cap);
+    build_lm_blocks(L, L.block_obs);
 }
 
 // Workspace carve-up: every array 256-byte aligned.
@@ -310,6 +310,7 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
         double* e = c.take<double>(2 * M * kCamRec);
         p.cbar[par][0] = e;
         p.cbar[par][1] = e ? e + M * kCamRec : nullptr;
+        p.cpk32[par] = fp32 ? c.take<float>(2 * M * 2 * kCamRec) : nullptr;
     }
     // the two candidates of a parity are one allocation (the observation
     // pass addresses candidate 1 as candidate 0 plus N records)
@@ -472,6 +473,17 @@ void write_point(daba_handle* h, const double* cams, const double* lms, const do
             upload(p.cams[k % 3], buf.data(), bytes, st);
             upload(p.ccand[par][0], buf.data(), bytes, st);
             upload(p.ccand[par][1], buf.data(), bytes, st);
+            if (h->opt.precision == DABA_FP32_MIXED) {
+                // both candidates' FP32 halves; the extrapolated halves follow
+                // from the extrapolation launch below
+                std::vector<float> bf(2 * L.M * 2 * kCamRec, 0.0f);
+                for (int c = 0; c < 2; ++c)
+                    for (int64_t ci = 0; ci < L.M; ++ci)
+                        for (int a = 0; a < kCamRec; ++a)
+                            bf[((size_t)c * L.M + ci) * 2 * kCamRec + a] = (float)buf[(size_t)ci * kCamRec + a];
+                upload(p.cpk32[par], bf.data(), bf.size() * sizeof(float), st);
+                hipcheck(hipStreamSynchronize(st), "sync");
+            }
         } else {
             upload(p.cams[(k + 2) % 3], buf.data(), bytes, st);
         }

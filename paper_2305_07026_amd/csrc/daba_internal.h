@@ -32,7 +32,7 @@ namespace daba {
 constexpr int kWave = 64;
 constexpr int kObsWaves = 4;         // waves (tiles) per block of the observation pass
 constexpr int kTileMax = 1024;       // most observations per tile (16 per lane)
-constexpr int kTileMin = 256;        // fewest observations per tile cap
+constexpr int kTileMin = 256;        // fewest observations per landmark block (target)
 constexpr int kMom = 38;             // moments of one surrogate
 constexpr int kTileVals = 80;        // 2 * 38 moments, F share, gap share, pad
 constexpr int kCamRec = 16;          // doubles per camera record
@@ -109,6 +109,11 @@ struct Params {
     double* cams[3];          // chosen x^k in generation k % 3
     double* ccand[2][2];      // [parity][0: plain MM, 1: accelerated] camera candidates
     double* cbar[2][2];       // x-bar the next iteration uses if that candidate is chosen
+    // FP32-mixed: per parity, both candidates (candidate c of camera i at
+    // c M + i), each a 128-byte line holding the candidate's FP32 record
+    // (16 floats) and that of its extrapolation, as the landmark pass reads
+    // them: one cache line per observation
+    float* cpk32[2];
     double* lcp[2][2];        // [parity][candidate] landmark pair records
     float* lcp32[2][2];
     int* restart;             // [S] restart test of the last decided iteration

@@ -845,42 +845,47 @@ __device__ __forceinline__ SlotObs<float> read_slot<float>(const Params& p, int6
     return {u.x, u.y, p.slot_cam[s]};
 }
 
-// Camera records of a landmark step in LDS: version 0 is x^k, version 1
-// x-bar^k, kCamSlab bytes apart.  The 64 records of a version (one per lane)
+// Camera records of a landmark step in LDS.  Each lane's camera arrives as
+// one or two 128-byte records: in FP64 the x^k record (16 doubles) and, for
+// the accelerated surrogate, the x-bar^k record, one slab apart; in
+// FP32-mixed one record holding both FP32 copies (x^k in the first 64
+// bytes, x-bar^k in the second).  The 64 records of a slab (one per lane)
 // arrive by LDS DMA in eight wave instructions, eight lanes per record, each
-// lane of a group loading the next 16 bytes of the record's line, so that
-// the addresser sees in-order runs (one record per 8 lanes) and a wave
-// instruction touches 8 cache lines.  Instruction i brings the records of
-// lanes i, 8 + i, ..., 56 + i into the 1 KB at 1040 i: the record of lane M
-// starts at 1040 (M mod 8) + 128 (M / 8).  The 16-byte skew between the
-// slabs puts chunk j of the records of any 16 consecutive lanes in 16
-// different bank groups, so that every lane reading chunk j of its own
-// record is conflict free, and chunk j is an immediate offset from the
-// lane's base.  `rec` is the lane's camera record index in the candidate
-// pair of allocations (candidate * M + camera); base0 / base1 are the x^k and
-// x-bar^k allocations of the parity.
-constexpr int kCamSlab = 8320;  // 1040 * 7 + 1024, rounded up to 16 bytes
-template <bool ACC>
-__device__ __forceinline__ void dma_cams(const double* __restrict__ base0, const double* __restrict__ base1,
-                                         unsigned rec, char* lds) {
+// lane of a group loading the next 16 bytes of the record, so that the
+// addresser sees in-order runs and a wave instruction touches 8 cache
+// lines.  Instruction i brings the records of lanes i, 8 + i, ..., 56 + i
+// into the 1 KB at 1040 i: the record of lane M starts at
+// 1040 (M mod 8) + 128 (M / 8).  The 16-byte skew between the slabs puts
+// chunk j of the records of any 16 consecutive lanes in 16 different bank
+// groups, so that every lane reading chunk j of its own record is conflict
+// free, and chunk j is an immediate offset from the lane's base.  `rec` is
+// the lane's record index in the candidate pair of allocations
+// (candidate * M + camera).
+constexpr int kCamSlab = 7 * 1040 + 1024 + 16;
+template <int NSETS>
+__device__ __forceinline__ void dma_cams(const void* __restrict__ base0, const void* __restrict__ base1, unsigned rec,
+                                         char* lds) {
     const int lane = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const unsigned w = (unsigned)__shfl((int)rec, (lane & ~7) + i);
-        const unsigned off = w * (unsigned)(kCamRec * sizeof(double)) + 16u * (unsigned)(lane & 7);
+        const unsigned off = w * 128u + 16u * (unsigned)(lane & 7);
         dma16(reinterpret_cast<const char*>(base0) + off, lds + 1040 * i);
-        if constexpr (ACC) dma16(reinterpret_cast<const char*>(base1) + off, lds + kCamSlab + 1040 * i);
+        if constexpr (NSETS == 2) dma16(reinterpret_cast<const char*>(base1) + off, lds + kCamSlab + 1040 * i);
     }
 }
-// Version v of the lane's record from LDS (rb: the lane's record offset).
+// Version v (0: x^k, 1: x-bar^k) of the lane's camera from LDS (rb: the
+// lane's record offset), in the evaluation type.
 template <typename R>
 __device__ __forceinline__ CamT<R> lds_cam(const char* lds, int rb, int v) {
-    double x[16];
+    typedef typename std::conditional<std::is_same<R, double>::value, double, float>::type T;
+    constexpr int C = (int)sizeof(T);  // chunks of one version
+    const char* src = sizeof(T) == 8 ? lds + kCamSlab * v + rb : lds + rb + 64 * v;
+    T x[16];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const double2 c = *reinterpret_cast<const double2*>(lds + kCamSlab * v + rb + 16 * j);
-        x[2 * j] = c.x;
-        x[2 * j + 1] = c.y;
+    for (int j = 0; j < C; ++j) {
+        const float4 c = *reinterpret_cast<const float4*>(src + 16 * j);
+        __builtin_memcpy(&x[j * (16 / C)], &c, 16);
     }
     CamT<R> o;
 #pragma unroll
@@ -934,8 +939,11 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
     const int par = (k + 1) & 1;
     const int lcc = chosen(restart, uniform_int(p.lmblock_part[lb]));
     const double* __restrict__ lpb = p.lcp[par][lcc];
-    const double* __restrict__ ckb = p.ccand[par][0];
-    const double* __restrict__ cbb = p.cbar[par][0];
+    // the records of the parity's candidates, and how many per camera
+    constexpr bool kF64 = sizeof(R) == 8;
+    constexpr int kSets = (kF64 && ACC) ? 2 : 1;
+    const void* ckb = kF64 ? (const void*)p.ccand[par][0] : (const void*)p.cpk32[par];
+    const void* cbb = p.cbar[par][0];
     const unsigned M = (unsigned)p.M;
     const double gam = ACC ? p.st[k & 1].gamma : 0.0;
     const R gamr = (R)gam;
@@ -958,31 +966,46 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
         const R lb0 = lk0 + gamr * (lk0 - lp0), lb1 = lk1 + gamr * (lk1 - lp1), lb2 = lk2 + gamr * (lk2 - lp2);
         double W0 = 0.0, V0[3] = {0.0, 0.0, 0.0}, W1 = 0.0, V1[3] = {0.0, 0.0, 0.0};
         // slot q of this lane's landmark at base + q n
-        // Slot q + 1 is in s1 and slot q + 2 is loaded during step q; every
-        // step issues the same loads (the prefetch past the last slot
-        // re-reads it), so that the compiler's wait counts stay exact.
+        // Step q's camera records wait in LDS when the step starts; they are
+        // read into registers, and step q + 1's DMA is issued before step q
+        // is evaluated, so that the DMA's latency overlaps the arithmetic.
+        // Slot q + 1 is in s0 and slot q + 2 in s1 (loaded during step
+        // q - 1); the prefetch past the last slot re-reads it, so that every
+        // step issues the same loads and the compiler's wait counts stay
+        // exact.
         auto slot_at = [&](int q) { return base + (int64_t)min(q, D - 1) * n; };
-        SlotObs<R> s0{}, s1{};
-        if (D > 0) {
-            s0 = read_slot<R>(p, slot_at(0));
-            s1 = read_slot<R>(p, slot_at(1));
-        }
-        for (int q = 0; q < D; ++q) {
-            const SlotObs<R> cur = s0;
+        auto rec_of = [&](unsigned cam) {
             // the record of the candidate the camera's partition chose
-            const unsigned rec = (unsigned)chosen(restart, (int)(cur.cam >> kCamBits)) * M + (cur.cam & kCamMask);
-            dma_cams<ACC>(ckb, cbb, rec, lds);
-            // the prefetch must be issued after every DMA, for the count below
+            return (unsigned)chosen(restart, (int)(cam >> kCamBits)) * M + (cam & kCamMask);
+        };
+        if (D > 0) {
+            SlotObs<R> s0 = read_slot<R>(p, slot_at(0));
+            SlotObs<R> s1 = read_slot<R>(p, slot_at(1));
+            R ux = s0.ux, uy = s0.uy;
+            dma_cams<kSets>(ckb, cbb, rec_of(on ? s0.cam : 0u), lds);
             __builtin_amdgcn_sched_barrier(0);
             s0 = s1;
-            s1 = read_slot<R>(p, slot_at(q + 2));
-            wait_vmem_n<2>();  // the DMAs; the two loads of slot q + 2 stay in flight
-            if (on) {
-                lm_terms<LOSS, R>(lds_cam<R>(lds, rb, 0), lk0, lk1, lk2, cur.ux, cur.uy, delta, W0, V0);
-                if constexpr (ACC)
-                    lm_terms<LOSS, R>(lds_cam<R>(lds, rb, 1), lb0, lb1, lb2, cur.ux, cur.uy, delta, W1, V1);
+            s1 = read_slot<R>(p, slot_at(2));
+            wait_vmem_n<2>();  // step 0's records; slot 2 stays in flight
+            for (int q = 0; q < D; ++q) {
+                const CamT<R> xk = lds_cam<R>(lds, rb, 0);
+                CamT<R> xb;
+                if constexpr (ACC) xb = lds_cam<R>(lds, rb, 1);
+                const R cux = ux, cuy = uy;
+                wait_lds();  // the records are in registers; the LDS is free
+                if (q + 1 < D) dma_cams<kSets>(ckb, cbb, rec_of(on ? s0.cam : 0u), lds);
+                ux = s0.ux;
+                uy = s0.uy;
+                __builtin_amdgcn_sched_barrier(0);
+                s0 = s1;
+                s1 = read_slot<R>(p, slot_at(q + 3));
+                __builtin_amdgcn_sched_barrier(0);
+                if (on) {
+                    lm_terms<LOSS, R>(xk, lk0, lk1, lk2, cux, cuy, delta, W0, V0);
+                    if constexpr (ACC) lm_terms<LOSS, R>(xb, lb0, lb1, lb2, cux, cuy, delta, W1, V1);
+                }
+                wait_vmem_n<2>();  // step q + 1's records; slot q + 3 stays in flight
             }
-            wait_lds();
         }
         if (!on) continue;
         // closed forms: l = l^y + V / (2W + xi) about each linearization point
@@ -1040,7 +1063,7 @@ __global__ __launch_bounds__(kWave) void k_tiles(Params p, int k) {
 
 template <typename R, int LOSS, bool ACC>
 __global__ __launch_bounds__(kWave) void k_lms(Params p, int k) {
-    __shared__ __align__(16) char cams[(ACC ? 2 : 1) * kCamSlab];
+    __shared__ __align__(16) char cams[(sizeof(R) == 8 && ACC ? 2 : 1) * kCamSlab];
     lm_role<R, LOSS, ACC>(p, k, blockIdx.x, cams);
 }
 
@@ -1059,6 +1082,19 @@ __device__ __forceinline__ CamD load_camd(const double* __restrict__ c) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) o.d[a] = c[12 + a];
     return o;
+}
+// A camera record (16 doubles) as its FP32 copy (16 floats).
+__device__ __forceinline__ void store_rec32(float* __restrict__ d, const double* __restrict__ c) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+        reinterpret_cast<float4*>(d)[a] =
+            make_float4((float)c[4 * a], (float)c[4 * a + 1], (float)c[4 * a + 2], (float)c[4 * a + 3]);
+}
+__device__ __forceinline__ void store_camd(double* __restrict__ c, const CamD& o);
+__device__ __forceinline__ void store_cam32(float* __restrict__ d, const CamD& o) {
+    double c[16];
+    store_camd(c, o);
+    store_rec32(d, c);
 }
 __device__ __forceinline__ void store_camd(double* __restrict__ c, const CamD& o) {
 #pragma unroll
@@ -1417,6 +1453,7 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, CamLd
         double phi;
         const CamD c = lm_camera(mom, y, xi, p.inner_steps, &phi);
         store_camd(p.ccand[k & 1][surr] + o, c);
+        if (p.fp32) store_cam32(p.cpk32[k & 1] + ((size_t)surr * p.M + ci) * 2 * kCamRec, c);
         if constexpr (ACC) {
             // the extrapolation the next iteration uses if this candidate is
             // chosen; gamma^(k+1) depends only on s^(k), so it is known now
@@ -1429,6 +1466,7 @@ __device__ __forceinline__ void camera_role(const Params& p, int k, int b, CamLd
             double* dst = p.cbar[k & 1][surr] + o;
 #pragma unroll
             for (int q = 0; q < 16; ++q) dst[q] = cbar[q];
+            if (p.fp32) store_rec32(p.cpk32[k & 1] + ((size_t)surr * p.M + ci) * 2 * kCamRec + kCamRec, cbar);
             if (surr == 1) store_camd(sh.c[cl], c);
         }
         // about y = x^k, the accepted change is the plain surrogate's change
@@ -1526,6 +1564,18 @@ __global__ __launch_bounds__(256) void k_finalize(Params p, int k) {
             reinterpret_cast<double2*>(p.cbar[par][1] + o)[a] = xb[a];
             reinterpret_cast<double2*>(p.cams[k % 3] + o)[a] = x[a];
         }
+        if (p.fp32) {
+            float4* r0 = reinterpret_cast<float4*>(p.cpk32[par] + (size_t)ci * 2 * kCamRec);
+            float4* r1 = reinterpret_cast<float4*>(p.cpk32[par] + ((size_t)p.M + ci) * 2 * kCamRec);
+            float4 y[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) y[a] = c ? r1[a] : r0[a];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                r0[a] = y[a];
+                r1[a] = y[a];
+            }
+        }
         return;
     }
     const int64_t j = i - p.M;
@@ -1567,6 +1617,10 @@ __global__ __launch_bounds__(256) void k_extrapolate_cams(Params p, int k) {
     for (int a = 0; a < 16; ++a) {
         p.cbar[par][0][(size_t)ci * kCamRec + a] = cb[a];
         p.cbar[par][1][(size_t)ci * kCamRec + a] = cb[a];
+    }
+    if (p.fp32) {
+        store_rec32(p.cpk32[par] + (size_t)ci * 2 * kCamRec + kCamRec, cb);
+        store_rec32(p.cpk32[par] + ((size_t)p.M + ci) * 2 * kCamRec + kCamRec, cb);
     }
 }
 
