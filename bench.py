@@ -1,11 +1,12 @@
 """Benchmark of the DABA iteration on one MI355X.
 
 One step = one DABA iteration (Algorithm 1's loop body) over the whole
-synthetic problem.  Default workload: 1,000 cameras, 200,000 landmarks,
-~1.6M observations, 8 camera partitions, Huber loss, FP64 (the configuration
-the headline metric is quoted on).  Prints one JSON line.
+synthetic problem.  Default workload: 20,000 cameras, 10,000,000 landmarks,
+~60M observations (track lengths 2 + Geometric(1/5)), 64 camera partitions,
+Huber loss: the largest configuration of the metric, FP64 against
+FP32-mixed at equal final objective.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cam1k-lm200k]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cam20k-lm10m]
                   [--no-cpu-baseline] [--no-fp32] [--no-attainable] [--copy-calibration MB]
                   [--surrogate entity|partition]
 
@@ -33,20 +34,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def obs_pass_bytes(sol, layout_T: int, fp32: bool, accelerate: bool) -> float:
-    """Algorithmic bytes one launch of the observation pass must move.
+SURVEY_BYTES_PER_OBS = 260.0   # whole iteration, reference design with a contribution buffer, S > 1
 
-    Per observation (FP64 / FP32-mixed): the pixel (16 / 8), the landmark
-    index and the landmark-side slot (4 + 4), from the landmark pair record
-    l^k, l^(k-1) and the partition id (52 / 28), and the landmark-side record
-    written at the slot (64 / 32; half without acceleration).  Per tile: three
-    camera records read (3 x 120 B), 78 moment / share sums written (624 B)
-    and the partition bins (16 S B)."""
-    per_obs = (8 if fp32 else 16) + 8 + (28 if fp32 else 52)
-    rec = (32 if fp32 else 64) if accelerate else (16 if fp32 else 32)
-    per_obs += rec
-    per_tile = 3 * 120 + 78 * 8 + 16 * sol.S
-    return per_obs * sol.K + per_tile * layout_T
+
+def kernel_bytes(prob, S: int, T: int, fp32: bool) -> dict:
+    """Algorithmic HBM bytes one launch of each observation-pass kernel must
+    move (FP64 / FP32-mixed):
+
+    k_tiles, per observation: the pixel (16 / 8), the landmark index (4) and
+    the used part of the landmark's pair record, l^k, partition, l^(k-1)
+    (52 / 28); per tile: three camera records read (3 x 120), the 76 moment
+    and 2 share sums written (624) and the partition bins (16 S).
+
+    k_lms, per observation: the pixel and the camera index at the slot
+    (16 / 8 + 4); per landmark: its pair record read (52) and both candidate
+    records written (2 x 56, plus 2 x 28 for the FP32 copies) (the two sums
+    per block, about 16 bytes per 1,000 observations, are left out).  The
+    camera records each observation gathers (2 x 128 / 128 bytes) come from
+    cache and are counted apart."""
+    K, N = prob["n_obs"], prob["n_landmarks"]
+    tiles = ((8 if fp32 else 16) + 4 + (28 if fp32 else 52)) * K + (3 * 120 + 78 * 8 + 16 * S) * T
+    lms = ((8 if fp32 else 16) + 4) * K + (52 + 2 * 56 + (2 * 28 if fp32 else 0)) * N
+    cache = (128 if fp32 else 256) * K
+    return {"k_tiles": float(tiles), "k_lms": float(lms), "k_lms_camera_gathers_from_cache": float(cache)}
 
 
 _CSRC = os.path.join(ROOT, "paper_2305_07026_amd", "csrc")
@@ -69,11 +79,11 @@ def source_digest(paths=KERNEL_SOURCES) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, precision: str):
-    """HBM bytes per launch of the observation pass from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated against a device
-    copy), if they were taken on the kernel code as it is now; else None."""
-    rec = os.path.join(ROOT, "profiles", f"k_obs_traffic_{workload}_{precision}.json")
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (calibrated against a device copy), if
+    they were taken on the kernel code as it is now; else None."""
+    rec = os.path.join(ROOT, "profiles", f"{kernel}_traffic_{workload}_{precision}.json")
     if not os.path.exists(rec):
         return None
     t = json.load(open(rec))
@@ -83,8 +93,20 @@ def measured_traffic(workload: str, precision: str):
 
 
 def n_tiles(prob) -> int:
+    """Camera tiles of the layout: each camera's observations in pieces of at
+    most 1,024."""
     cnt = __import__("numpy").bincount(prob["obs_camera"], minlength=prob["n_cameras"])
     return int(sum(-(-int(c) // 1024) for c in cnt))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def equal_objective(prob, ms64, ms32, iters, S, make):
@@ -96,12 +118,26 @@ def equal_objective(prob, ms64, ms32, iters, S, make):
     F0 = a.objective()
     F64 = a.iterate(iters)
     b = make("fp32_mixed")
-    F32 = b.iterate(int(iters * 1.5))
+    F32a = b.iterate(iters)
+    # the FP32-mixed iterate against the FP64 one after the same iterations:
+    # largest relative difference per column group (R, t, f, k1, k2, l)
+    sa, sb = a.get_state(), b.get_state()
+    ca, cb, la, lb = sa["cams"], sb["cams"], sa["lms"], sb["lms"]
+
+    def rel(x, y):
+        return float(np.max(np.abs(x - y)) / max(np.max(np.abs(x)), 1e-300))
+    groups = {"R": slice(0, 9), "t": slice(9, 12), "f": slice(12, 13), "f k1": slice(13, 14), "f k2": slice(14, 15)}
+    state_err = {g: rel(ca[:, sl], cb[:, sl]) for g, sl in groups.items()}
+    state_err["l"] = rel(la, lb)
+    del a
+    F32 = np.concatenate([F32a, b.iterate(iters // 2)])
+    del b
     target = F64[-1] + 1e-4 * (F0 - F64[-1])
     n64 = int(np.argmax(F64 <= target)) + 1 if np.any(F64 <= target) else None
     n32 = int(np.argmax(F32 <= target)) + 1 if np.any(F32 <= target) else None
     out = dict(F_init=F0, F_fp64_final=float(F64[-1]), F_target=float(target), iters_fp64=n64, iters_fp32=n32,
-               fp32_rel_err_at_fp64_final_iter=float(abs(F32[iters - 1] - F64[-1]) / F64[-1]))
+               fp32_rel_err_at_fp64_final_iter=float(abs(F32[iters - 1] - F64[-1]) / F64[-1]),
+               fp32_vs_fp64_state_rel_err_after_iters=state_err)
     if n64 and n32:
         out["time_fp64_ms"] = n64 * ms64
         out["time_fp32_ms"] = n32 * ms32
@@ -111,13 +147,15 @@ def equal_objective(prob, ms64, ms32, iters, S, make):
     return out
 
 
-def cpu_baseline(prob, S, budget_s=15.0, budget_1t_s=6.0):
+def cpu_baseline(prob, S, budget_s=15.0, budget_1t_s=6.0, one_thread=True):
     """The oracle, as it stands, on the same problem and options: whole
     iterations from x^0 until about budget_s of CPU work has been done on
-    every host core, then (continuing from there) about budget_1t_s on one
-    thread."""
+    every host core, then (continuing from there, if one_thread) about
+    budget_1t_s on one thread."""
     from oracle import Oracle, num_threads, set_num_threads
+    t0 = time.perf_counter()
     o = Oracle(prob, n_partitions=S, loss="huber", delta=1.0, xi=1e-9, eta=0.5)
+    setup = time.perf_counter() - t0
 
     def run(budget):
         n, t0 = 0, time.perf_counter()
@@ -130,14 +168,18 @@ def cpu_baseline(prob, S, budget_s=15.0, budget_1t_s=6.0):
 
     cores = num_threads()
     n, dt = run(budget_s)
-    set_num_threads(1)
-    n1, dt1 = run(budget_1t_s)
-    set_num_threads(0)
-    return dict(value=prob["n_obs"] * n / dt, unit="obs*iter/s", cores=cores, kind="oracle",
-                sample=f"{n} oracle iteration(s) of the same {prob['n_obs']}-observation problem from x^0, "
-                       f"{dt:.1f} s wall, OpenMP over entities",
-                value_1thread=prob["n_obs"] * n1 / dt1,
-                sample_1thread=f"the next {n1} iteration(s) on 1 thread, {dt1:.1f} s wall")
+    out = dict(value=prob["n_obs"] * n / dt, unit="obs*iter/s", cores=cores, kind="oracle",
+               sample=f"{n} oracle iteration(s) of the same {prob['n_obs']}-observation problem from x^0, "
+                      f"{dt:.1f} s wall (oracle setup {setup:.1f} s not counted), OpenMP over entities",
+               cpu_model=cpu_model())
+    if one_thread:
+        set_num_threads(1)
+        n1, dt1 = run(budget_1t_s)
+        set_num_threads(0)
+        out["value_1thread"] = prob["n_obs"] * n1 / dt1
+        out["sample_1thread"] = f"the next {n1} iteration(s) on 1 thread, {dt1:.1f} s wall"
+    del o
+    return out
 
 
 def attainable_bandwidth(mib=1024, reps=10, grids=(512, 768, 1024, 1280)):
@@ -253,9 +295,9 @@ def bench_partition(args, prob, S):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="cam1k-lm200k")
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cam20k-lm10m")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -292,45 +334,49 @@ def main():
     def make(prec):
         return P.DabaSolver(prob, precision=prec, **opts)
 
-    log("create")
-    t0 = time.perf_counter()
-    sol = make(args.precision)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-
-    log(f"warmup {args.warmup}")
-    sol.iterate(args.warmup, trace=False)
-    torch.cuda.synchronize()
-    stream = sol.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    log(f"timed {args.steps}")
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    sol.iterate(args.steps, trace=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_ms = e0.elapsed_time(e1)
-    ms_per_step = gpu_ms / args.steps
-    value = K * args.steps / (gpu_ms / 1e3)
-    # two more timed regions of the same length, for the spread
-    repeats = [ms_per_step]
-    for _ in range(2):
-        e0.record(stream)
-        sol.iterate(args.steps, trace=False)
-        e1.record(stream)
+    def timed(sol, steps):
+        """GPU ms per iteration over `steps` graph-replayed iterations, with
+        HIP events on the solver's stream."""
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        repeats.append(e0.elapsed_time(e1) / args.steps)
+        e0.record(sol.stream)
+        sol.iterate(steps, trace=False)
+        e1.record(sol.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
 
-    # per-kernel durations from HIP events around each launch, over the same
-    # number of steps of the same run (instrumented launches, no graph)
-    log("kernel timing")
-    kern = sol.iterate_timed(args.steps) / args.steps
-    fp32 = args.precision == "fp32_mixed"
-    nbytes = obs_pass_bytes(sol, T, fp32, True)
-    achieved = nbytes / (kern[0] / 1e3) / 1e9
+    def measure(prec):
+        log(f"create ({prec})")
+        t0 = time.perf_counter()
+        sol = make(prec)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        log(f"warmup {args.warmup} ({prec})")
+        sol.iterate(args.warmup, trace=False)
+        log(f"timed 3 x {args.steps} ({prec})")
+        w0 = time.perf_counter()
+        reps = [timed(sol, args.steps)]
+        wall = time.perf_counter() - w0
+        reps += [timed(sol, args.steps) for _ in range(2)]
+        # per-kernel durations from HIP events around each launch, over the
+        # same number of steps of the same run (instrumented launches, no graph)
+        log(f"kernel timing ({prec})")
+        kern = sol.iterate_timed(args.steps) / args.steps
+        return sol, reps, wall, kern, setup
+
+    prec = args.precision
+    fp32 = prec == "fp32_mixed"
+    sol, repeats, wall, kern, setup_s = measure(prec)
+    ms_per_step = repeats[0]
+    value = K / (ms_per_step / 1e3)
     F_final = sol.objective()
+    del sol
+    torch.cuda.empty_cache()
+    kb = kernel_bytes(prob, S, T, fp32)
+    names = ["k_tiles", "k_lms", "k_entity", "k_decide (+k_finalize once)"]
+    dom = "k_tiles" if kern[0] >= kern[1] else "k_lms"
+    dom_ms = kern[0] if dom == "k_tiles" else kern[1]
+    achieved = kb[dom] / (dom_ms / 1e3) / 1e9
     attainable = None
     if not (args.no_attainable or args.copy_calibration):
         log("copy bandwidth")
@@ -351,41 +397,43 @@ def main():
         "data": "synthetic (seeded generator standing in for the paper's BAL/1DSfM scenes)",
         "config": {"workload": f"{args.workload}: {prob['n_cameras']} cameras, {prob['n_landmarks']} landmarks, "
                                f"{K} observations, {S} camera partitions, Huber delta=1px, DABA (Nesterov + "
-                               f"adaptive restart), 1 inner LM step, {args.precision}",
+                               f"adaptive restart), 1 inner LM step, {prec}",
                    "n_cameras": prob["n_cameras"], "n_landmarks": prob["n_landmarks"], "n_obs": K,
-                   "n_partitions": S, "precision": args.precision},
-        "roofline": {"bound": "hbm", "kernel": "k_obs_dma (observation pass)", "achieved": achieved,
+                   "n_partitions": S, "precision": prec},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, args.precision),
-                     "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": kern[0],
+                     "traffic": measured_traffic(dom, args.workload, prec),
+                     "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": dom_ms,
                      "attainable_copy_GBs": attainable,
                      "frac_of_attainable": achieved / attainable if attainable else None},
+        "kernels": {n: {"ms": float(kern[i]),
+                        "algorithmic_bytes": kb.get(n),
+                        "GBs": kb[n] / (kern[i] / 1e3) / 1e9 if n in kb else None,
+                        "traffic": measured_traffic(n, args.workload, prec) if n in kb else None}
+                    for i, n in enumerate(names)},
+        "k_lms_camera_gathers_from_cache_bytes": kb["k_lms_camera_gathers_from_cache"],
+        "iteration_at_survey_bytes": {
+            "bytes_per_obs": SURVEY_BYTES_PER_OBS,
+            "GBs": SURVEY_BYTES_PER_OBS * K / (ms_per_step / 1e3) / 1e9,
+            "frac": SURVEY_BYTES_PER_OBS * K / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "ms_per_step_repeats": repeats,
         "ms_per_step_median": sorted(repeats)[1],
-        "kernel_ms_per_step": {"k_tiles": kern[0], "k_lms": kern[1], "k_entity": kern[2],
-                               "k_decide (+k_finalize once)": kern[3]},
         "wall_s_timed_region": wall,
         "setup_s": setup_s,
         "F_after": F_final,
     }
-    if not args.no_fp32 and args.precision == "fp64":
-        log("fp32-mixed")
-        s32 = make("fp32_mixed")
-        s32.iterate(args.warmup, trace=False)
-        torch.cuda.synchronize()
-        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        f0.record(s32.stream)
-        s32.iterate(args.steps, trace=False)
-        f1.record(s32.stream)
-        torch.cuda.synchronize()
-        ms32 = f0.elapsed_time(f1) / args.steps
-        k32 = s32.iterate_timed(args.steps) / args.steps
-        b32 = obs_pass_bytes(s32, T, True, True)
+    if not args.no_fp32 and not fp32:
+        s32, reps32, _, k32, _ = measure("fp32_mixed")
+        ms32 = reps32[0]
         del s32
+        torch.cuda.empty_cache()
+        kb32 = kernel_bytes(prob, S, T, True)
         log("equal objective")
         eq = equal_objective(prob, ms_per_step, ms32, cfg["iterations"] or 200, S, make)
-        out["fp32_mixed"] = {"value": K / (ms32 / 1e3), "ms_per_step": ms32,
-                             "k_obs_ms": k32[0], "k_obs_GBs": b32 / (k32[0] / 1e3) / 1e9,
+        out["fp32_mixed"] = {"value": K / (ms32 / 1e3), "ms_per_step": ms32, "ms_per_step_repeats": reps32,
+                             "kernels": {n: {"ms": float(k32[i]),
+                                             "GBs": kb32[n] / (k32[i] / 1e3) / 1e9 if n in kb32 else None}
+                                         for i, n in enumerate(names)},
                              "equal_objective": eq}
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 8
@@ -397,7 +445,7 @@ def main():
         out["copy_calibration_bytes"] = 2 * n * 8
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(prob, S)
+        out["cpu_baseline"] = cpu_baseline(prob, S, one_thread=K <= 20_000_000)
     print(json.dumps(out), flush=True)
 
 
