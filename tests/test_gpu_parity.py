@@ -11,6 +11,7 @@ checked at 1e-12 / 1e-10.  The FP32-mixed path matches the FP64 oracle to
 import numpy as np
 import pytest
 
+from compare import assert_state_close, state_errs
 from oracle import ALWAYS_RESTART, Oracle
 from synth import make_problem
 
@@ -121,9 +122,8 @@ def test_state_after_iterations(c1):
     g.iterate(30, trace=False)
     o.iterate(30)
     sg, so = g.get_state(), o.get_state()
-    assert nrel(sg["cams"], so["cams"]) <= 1e-10
-    assert nrel(sg["lms"], so["lms"]) <= 1e-10
-    assert nrel(sg["cams_prev"], so["cams_prev"]) <= 1e-10
+    assert_state_close(sg, so, 1e-10, "x^30")
+    assert_state_close(sg, so, 1e-10, "x^29", cams_key="cams_prev", lms_key="lms_prev")
     assert sg["k"] == so["k"] == 30 and sg["s"] == so["s"]
     assert rel(sg["part"], so["part"]) <= 1e-9
 
@@ -139,8 +139,7 @@ def test_one_step_parity_from_common_state(c1):
     Fo, mo = o.iterate(1)
     assert rel(Fg, Fo) <= 1e-12
     sg, so = g.get_state(), o.get_state()
-    assert nrel(sg["cams"], so["cams"]) <= 1e-12
-    assert nrel(sg["lms"], so["lms"]) <= 1e-12
+    assert_state_close(sg, so, 1e-11, "one step")
     assert np.array_equal(g.metrics()[:, 3], mo[0, :, 3])
 
 
@@ -167,6 +166,8 @@ def test_objective_and_gradient_at_caller_point(tiled):
     gc, gl, gu = (t.cpu().numpy() for t in g.grad(dev(cams), dev(lms), dev(uv)))
     oc, ol, ou = o.grad(cams, lms, uv)
     assert nrel(gl, ol) <= 1e-10 and nrel(gu, ou) <= 1e-10 and nrel(gc[:, :12], oc[:, :12]) <= 1e-10
+    for k in range(12, 15):
+        assert nrel(gc[:, k], oc[:, k]) <= 1e-10
     # the stored point is untouched
     assert rel(g.objective(), o.objective()) <= 1e-12
 
@@ -209,13 +210,26 @@ def test_converged_inner_solver(tiled):
 
 
 def test_fp32_mixed_within_1e4_after_100(c1):
+    """FP32-mixed against the FP64 oracle, per result: the objective after
+    100 iterations within 1e-4 (the requirement), and, stated and bounded,
+    the objective on every iteration, the iterate per column group and the
+    restart decisions."""
     g = P.DabaSolver(c1, n_partitions=4, loss="huber", precision="fp32_mixed")
     o = Oracle(c1, n_partitions=4, loss="huber")
-    Fg = g.iterate(100)
-    Fo, _ = o.iterate(100)
+    Fo, mo = o.iterate(100)
+    Fg = np.empty(100)
+    flags = np.empty((100, 4))
+    for k in range(100):
+        Fg[k] = g.iterate(1)[0]
+        flags[k] = g.metrics()[:, 3]
     r = np.abs(Fg - Fo) / Fo
+    agree = float(np.mean(flags == mo[:, :, 3]))
+    print(f"FP32-mixed vs oracle: F after 100 {r[-1]:.1e}, worst iteration {r.max():.1e}, "
+          f"restart decisions equal on {100 * agree:.1f}% of (iteration, partition) pairs", flush=True)
     assert r[-1] <= 1e-4, r[-1]
     assert r.max() <= 1e-3
+    assert agree >= 0.9
+    assert_state_close(g.get_state(), o.get_state(), 5e-3, "FP32-mixed iterate after 100")
 
 
 @pytest.mark.parametrize("loss", ["trivial", "welsch"])

@@ -9,7 +9,8 @@ reduced camera system).  A solve of a system with condition number kappa
 agrees to about kappa * 1e-16; with the damping and kappa <= 1e4 here that is
 1e-12 per step.  Every accept/reject decision is taken on a strict decrease of
 E^a and matches unless two values tie to that level.  The objective after each
-iteration is checked at 1e-9 relative, the final state at 1e-6 (the flat
+iteration is checked at 1e-10 relative, the final state per column group
+(rotation, translation, each intrinsic, landmarks) at 1e-6 (the flat
 intrinsic directions d2, d3 amplify step differences), the per-partition
 metrics at 1e-8.
 """
@@ -17,6 +18,7 @@ metrics at 1e-8.
 import numpy as np
 import pytest
 
+from compare import state_errs
 from oracle.partition import PartOracle
 from synth import make_problem
 
@@ -60,19 +62,24 @@ def run_both(prob, n, **kw):
     Fo, mo = o.iterate(n)
     st = g.get_state()
     c_o, l_o = o.get_state()
-    print(f"  F rel {rel(Fg, Fo):.2e}  cams {nrel(st['cams'][:, :12], c_o[:, :12]):.2e}  "
-          f"lms {nrel(st['lms'], l_o):.2e}  metrics {rel(st['metrics'][:, :3], mo[-1, :, :3]):.2e}", flush=True)
+    errs = state_errs(st, {"cams": c_o, "lms": l_o})
+    print(f"  F rel {rel(Fg, Fo):.2e}  state " + " ".join(f"{k} {v:.1e}" for k, v in errs.items())
+          + f"  metrics {rel(st['metrics'][:, :3], mo[-1, :, :3]):.2e}", flush=True)
+    st["errs"] = errs
     return g, o, Fg, Fo, st, mo
+
+
+def check_state(st, tol=1e-6):
+    bad = {k: v for k, v in st["errs"].items() if not v <= tol}
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("S,loss,acc", [(1, "trivial", False), (3, "huber", True), (4, "welsch", True),
                                         (2, "huber", False)])
 def test_iterations_match_the_oracle(small, S, loss, acc):
     g, o, Fg, Fo, st, mo = run_both(small, 8, n_partitions=S, loss=loss, accelerate=acc)
-    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
-    c_o, l_o = o.get_state()
-    assert nrel(st["lms"], l_o) <= 1e-6
-    assert nrel(st["cams"][:, :12], c_o[:, :12]) <= 1e-6
+    assert rel(Fg, Fo) <= 1e-10, (Fg, Fo)
+    check_state(st)
     np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
     assert rel(st["metrics"][:, :3], mo[-1, :, :3]) <= 1e-8
     g.close()
@@ -87,17 +94,33 @@ def test_custom_partitions_and_a_device_without_cameras(geom):
     lp = rng.integers(0, 3, N).astype(np.int32)
     g, o, Fg, Fo, st, mo = run_both(geom, 6, n_partitions=3, camera_partition=cp, landmark_partition=lp,
                                     loss="huber", accelerate=True)
-    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
+    assert rel(Fg, Fo) <= 1e-10, (Fg, Fo)
+    check_state(st)
     np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
 
 
 def test_inner_steps_and_restart_flags(small):
     g, o, Fg, Fo, st, mo = run_both(small, 5, n_partitions=3, loss="huber", inner_steps=3)
-    assert rel(Fg, Fo) <= 1e-9
+    assert rel(Fg, Fo) <= 1e-10
+    check_state(st)
     for flags in (1, 2):
         g, o, Fg, Fo, st, mo = run_both(small, 4, n_partitions=3, loss="huber", debug_flags=flags)
-        assert rel(Fg, Fo) <= 1e-9
+        assert rel(Fg, Fo) <= 1e-10
+        check_state(st)
         np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
+
+
+@pytest.mark.timeout(600)
+def test_eighteen_tile_reduced_system():
+    """One device with 130 cameras and 800 landmarks: the reduced camera
+    system has order 1,170, eighteen 64-tiles and a ragged nineteenth, as in
+    the benchmark's 1,000-camera, 8-partition workload (order 1,125); the
+    oracle solves the whole partition system (order about 3,600) densely."""
+    prob = make_problem("cam50-lm5k", n_cameras=130, n_landmarks=800, seed=47)
+    g, o, Fg, Fo, st, mo = run_both(prob, 4, n_partitions=1, loss="huber")
+    assert rel(Fg, Fo) <= 1e-10, (Fg, Fo)
+    check_state(st)
+    np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
 
 
 def test_bitwise_reproducible(small):
@@ -160,10 +183,8 @@ def test_proximal_term_matters(small, xi, scale):
     of the model Hessian, reading P4) shapes every step; with another unit
     scale the unit conversions are exercised too."""
     g, o, Fg, Fo, st, mo = run_both(small, 6, n_partitions=3, loss="huber", xi=xi, unit_scale=scale)
-    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
-    c_o, l_o = o.get_state()
-    assert nrel(st["lms"], l_o) <= 1e-6
-    assert nrel(st["cams"][:, :12], c_o[:, :12]) <= 1e-6
+    assert rel(Fg, Fo) <= 1e-10, (Fg, Fo)
+    check_state(st)
     np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
 
 
@@ -172,7 +193,8 @@ def test_restart_average_weights(small, loss, eta):
     """eq. lFak with other weights eta (eta = 1: the test compares with
     F^a(k) itself) and the trivial loss under acceleration."""
     g, o, Fg, Fo, st, mo = run_both(small, 10, n_partitions=3, loss=loss, eta=eta)
-    assert rel(Fg, Fo) <= 1e-9, (Fg, Fo)
+    assert rel(Fg, Fo) <= 1e-10, (Fg, Fo)
+    check_state(st)
     np.testing.assert_array_equal(st["metrics"][:, 3], mo[-1, :, 3])
     assert rel(st["metrics"][:, :3], mo[-1, :, :3]) <= 1e-8
 
