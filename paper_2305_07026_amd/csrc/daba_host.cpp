@@ -1011,8 +1011,24 @@ int daba_set_state(daba_handle* h, const double* cams, const double* lms, const 
         if (cc->l) std::memcpy(vl.data(), cc->l, vl.size() * sizeof(double));
         if (cc->cp) std::memcpy(vcp.data(), cc->cp, vcp.size() * sizeof(double));
         if (cc->lp) std::memcpy(vlp.data(), cc->lp, vlp.size() * sizeof(double));
+        // every input is checked before anything is changed, so that a call
+        // that fails leaves the handle as it was
+        for (const std::vector<double>* cs : {&vc, &vcp})
+            for (int64_t i = 0; i < L.M; ++i) {
+                const double* c = cs->data() + 15 * (size_t)i;
+                for (int a = 0; a < 15; ++a)
+                    if (!std::isfinite(c[a])) fail(DABA_E_INVAL, "camera %lld has a non-finite entry", (long long)i);
+                if (!rotation_ok(c)) fail(DABA_E_INVAL, "camera %lld: R is not a rotation", (long long)i);
+            }
+        for (const std::vector<double>* ls : {&vl, &vlp})
+            for (double v : *ls)
+                if (!std::isfinite(v)) fail(DABA_E_INVAL, "landmarks have a non-finite entry");
+        if (cc->sc && !(std::isfinite(cc->sc[0]) && cc->sc[0] >= 1.0 && std::isfinite(cc->sc[1]) && cc->sc[1] >= 0))
+            fail(DABA_E_INVAL, "bad scalars (s >= 1, k >= 0)");
+        if (cc->p4)
+            for (int q = 0; q < 4 * L.S; ++q)
+                if (!std::isfinite(cc->p4[q])) fail(DABA_E_INVAL, "part4 has a non-finite entry");
         if (cc->sc) {
-            if (!(cc->sc[0] >= 1.0) || cc->sc[1] < 0) fail(DABA_E_INVAL, "bad scalars (s >= 1, k >= 0)");
             const int64_t knew = (int64_t)cc->sc[1];
             DevState sts[2];
             download(sts, p.st, sizeof sts, s);

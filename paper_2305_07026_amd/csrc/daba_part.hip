@@ -2075,6 +2075,29 @@ int daba_part_set_checkpoint(daba_part_handle* h, const double* cams, const doub
     if (!h) return DABA_E_INVAL;
     try {
         hipck(hipStreamSynchronize(h->stream), "stream sync");
+        // every input is checked before anything is changed, so that a call
+        // that fails leaves the handle as it was
+        const PLayout& L = h->L;
+        for (const double* cs : {cams, cams_prev}) {
+            if (!cs) continue;
+            for (int64_t i = 0; i < L.M; ++i) {
+                const double* c = cs + 15 * (size_t)i;
+                for (int a = 0; a < 15; ++a)
+                    if (!std::isfinite(c[a])) fail(DABA_E_INVAL, "camera %lld has a non-finite entry", (long long)i);
+                if (!rotation_ok(c)) fail(DABA_E_INVAL, "camera %lld: R is not a rotation", (long long)i);
+            }
+        }
+        for (const double* ls : {lms, lms_prev}) {
+            if (!ls) continue;
+            for (int64_t j = 0; j < 3 * (int64_t)L.N; ++j)
+                if (!std::isfinite(ls[j])) fail(DABA_E_INVAL, "landmarks have a non-finite entry");
+        }
+        if (part3)
+            for (int a = 0; a < L.S; ++a) {
+                for (int c = 0; c < 3; ++c)
+                    if (!std::isfinite(part3[3 * a + c])) fail(DABA_E_INVAL, "part3 has a non-finite entry");
+                if (!(part3[3 * a + 2] >= 1.0)) fail(DABA_E_INVAL, "s^a must be >= 1");
+            }
         if (cams) upload_cams(h, cams, h->b.x_c);
         if (lms) upload_lms(h, lms, h->b.x_l);
         if (cams_prev) upload_cams(h, cams_prev, h->b.xp_c);
@@ -2085,9 +2108,6 @@ int daba_part_set_checkpoint(daba_part_handle* h, const double* cams, const doub
             hipck(hipMemcpy(ps.data(), h->p.ps, 8 * ps.size(), hipMemcpyDeviceToHost), "download");
             const double s2 = h->L.scale * h->L.scale;
             for (int a = 0; a < S; ++a) {
-                for (int c = 0; c < 3; ++c)
-                    if (!std::isfinite(part3[3 * a + c])) fail(DABA_E_INVAL, "part3 has a non-finite entry");
-                if (!(part3[3 * a + 2] >= 1.0)) fail(DABA_E_INVAL, "s^a must be >= 1");
                 ps[(size_t)a * kPS + P_FBAR] = part3[3 * a + 0] / s2;
                 ps[(size_t)a * kPS + P_E] = part3[3 * a + 1] / s2;
                 ps[(size_t)a * kPS + P_S] = part3[3 * a + 2];

@@ -277,3 +277,21 @@ def test_degenerate_point_is_reported(c1):
     with pytest.raises(P.binding.DabaError) as ei:
         g.iterate(1)
     assert ei.value.code == -5
+
+
+def test_rejected_set_state_changes_nothing(c1):
+    """A state with one camera that is not a rotation (and a new iteration
+    counter) is rejected before anything is written: the handle continues
+    exactly like an untouched one."""
+    a = P.DabaSolver(c1, n_partitions=4, loss="huber")
+    b = P.DabaSolver(c1, n_partitions=4, loss="huber")
+    a.iterate(5, trace=False)
+    b.iterate(5, trace=False)
+    bad = a.get_state()
+    bad["cams"] = bad["cams"].copy()
+    bad["cams"][3, :9] *= 1.5
+    bad["k"] = bad["k"] + 7
+    with pytest.raises(P.binding.DabaError):
+        a.set_state(bad)
+    assert np.array_equal(a.iterate(6), b.iterate(6))
+    assert np.array_equal(a.get_state()["cams"], b.get_state()["cams"])

@@ -214,3 +214,20 @@ def test_checkpoint_and_resume_bitwise(small):
     np.testing.assert_array_equal(np.r_[F_a, F_b], F_full)
     np.testing.assert_array_equal(second.get_state()["cams"], full.get_state()["cams"])
     np.testing.assert_array_equal(second.get_state()["metrics"], full.get_state()["metrics"])
+
+
+def test_rejected_checkpoint_changes_nothing(small):
+    """A checkpoint with a camera that is not a rotation is rejected before
+    anything is written."""
+    kw = dict(n_partitions=3, loss="huber")
+    a = P.DabaPartSolver(small, **kw)
+    b = P.DabaPartSolver(small, **kw)
+    a.iterate(3)
+    b.iterate(3)
+    ck = a.checkpoint()
+    ck["lms"] = ck["lms"] + 1.0
+    ck["cams_prev"] = ck["cams_prev"].copy()
+    ck["cams_prev"][2, :9] *= 1.5
+    with pytest.raises(P.binding.DabaError):
+        a.restore(ck)
+    np.testing.assert_array_equal(a.iterate(3), b.iterate(3))
