@@ -61,7 +61,8 @@ def kernel_bytes(prob, S: int, T: int, fp32: bool) -> dict:
 
 _CSRC = os.path.join(ROOT, "paper_2305_07026_amd", "csrc")
 # the iteration's kernels and the device headers they include
-KERNEL_SOURCES = tuple(os.path.join(_CSRC, f) for f in ("daba_kernels.hip", "daba_internal.h", "daba_rotation.h"))
+KERNEL_SOURCES = tuple(os.path.join(_CSRC, f) for f in ("daba_kernels.hip", "daba_internal.h", "daba_rotation.h",
+                                                   "daba_eval.h"))
 
 
 def source_digest(paths=KERNEL_SOURCES) -> str:

@@ -155,6 +155,31 @@ int daba_iterate_timed(daba_handle *h, int n_iters, double *ms_out);
  * DABA_E_HIP if the launch fails. */
 int daba_stream_copy(void *dst, const void *src, size_t bytes, int blocks, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the robust
+ * objective F = sum_ij 1/2 rho(|e_ij|^2) of Problem 1, as daba_objective
+ * computes it, at caller arrays, with no handle and no workspace.
+ *   n_cameras, n_landmarks >= 1; 0 <= n_obs <= DABA_NOALLOC_MAX_OBS;
+ *   obs_camera, obs_landmark: DEVICE int32 [n_obs]; obs_uv: DEVICE [n_obs*2]
+ *   pixels, principal point subtracted; cameras: DEVICE [n_cameras*15] in
+ *   the layout of daba_problem; landmarks: DEVICE [n_landmarks*3]; loss and
+ *   loss_delta (pixels) as in daba_options; F_out: DEVICE, one double, in
+ *   caller units.
+ * Enqueues on hip_stream and returns; allocates nothing (no hipMalloc, no
+ * host allocation).  Its only device memory beyond the arguments is a
+ * static array of DABA_NOALLOC_BLOCKS doubles per GPU, which the library
+ * holds until the process ends; every call on a GPU shares it, so calls
+ * that overlap on one GPU race and must be ordered by the caller.  Each
+ * call writes every entry it reads, so no clearing is needed.  An
+ * observation with an index out of range or a landmark at its camera centre
+ * (Assumption 2) makes *F_out NaN.  Returns DABA_E_INVAL for a bad size,
+ * pointer or loss (before any device work), DABA_E_HIP if the launch fails. */
+#define DABA_NOALLOC_BLOCKS 4096
+#define DABA_NOALLOC_MAX_OBS 2000000000LL
+int daba_objective_noalloc(int64_t n_cameras, int64_t n_landmarks, int64_t n_obs, const int32_t *obs_camera,
+                           const int32_t *obs_landmark, const double *obs_uv, const double *cameras,
+                           const double *landmarks, int loss, double loss_delta, double *F_out, void *hip_stream);
+
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 int daba_destroy(daba_handle *h);
 

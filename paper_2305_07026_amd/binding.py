@@ -78,6 +78,8 @@ def _load() -> C.CDLL:
     lib.daba_get_metrics.argtypes = [vp, pd]
     lib.daba_destroy.argtypes = [vp]
     lib.daba_stream_copy.argtypes = [vp, vp, C.c_size_t, i, vp]
+    i64 = C.c_int64
+    lib.daba_objective_noalloc.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, i, d, vp, vp]
     lib.daba_last_error.argtypes = [vp]
     lib.daba_last_error.restype = C.c_char_p
     # device-level surrogate (include/daba_part.h)
@@ -94,6 +96,7 @@ def _load() -> C.CDLL:
     lib.daba_part_last_error.restype = C.c_char_p
     for name in ("daba_create", "daba_iterate", "daba_iterate_timed", "daba_objective", "daba_grad",
                  "daba_get_state", "daba_set_state", "daba_get_metrics", "daba_destroy", "daba_stream_copy",
+                 "daba_objective_noalloc",
                  "daba_part_create", "daba_part_iterate", "daba_part_iterate_timed", "daba_part_get_state",
                  "daba_part_get_checkpoint", "daba_part_set_checkpoint", "daba_part_destroy"):
         getattr(lib, name).restype = C.c_int
@@ -113,3 +116,22 @@ def check_part(rc: int, where: str, handle=None):
     if rc != DABA_OK:
         detail = lib.daba_part_last_error(handle).decode()
         raise DabaError(rc, where, detail)
+
+
+def objective_noalloc(obs_camera, obs_landmark, obs_uv, cameras, landmarks, F_out, loss="huber", delta=1.0,
+                      stream=None):
+    """daba_objective_noalloc on torch device tensors (int32 observation
+    lists, float64 pixels, cameras [M, 15], landmarks [N, 3], F_out one
+    float64): enqueues on `stream` (default: torch's current stream) and
+    returns; raises DabaError for a rejected argument."""
+    import torch
+    M, N, K = cameras.shape[0], landmarks.shape[0], obs_camera.shape[0]
+    for t in (obs_camera, obs_landmark, obs_uv, cameras, landmarks, F_out):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("objective_noalloc takes contiguous device tensors")
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    rc = lib.daba_objective_noalloc(M, N, K, obs_camera.data_ptr(), obs_landmark.data_ptr(), obs_uv.data_ptr(),
+                                    cameras.data_ptr(), landmarks.data_ptr(), LOSS[loss], float(delta),
+                                    F_out.data_ptr(), s)
+    if rc != DABA_OK:
+        raise DabaError(rc, "daba_objective_noalloc", "argument rejected or launch failed")

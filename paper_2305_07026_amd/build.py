@@ -16,7 +16,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 SOURCES = [os.path.join(CSRC, "daba_kernels.hip"), os.path.join(CSRC, "daba_host.cpp"),
-           os.path.join(CSRC, "daba_probe.hip"), os.path.join(CSRC, "daba_part.hip")]
+           os.path.join(CSRC, "daba_probe.hip"), os.path.join(CSRC, "daba_part.hip"),
+           os.path.join(CSRC, "daba_noalloc.hip")]
 
 
 def build(verbose: bool = False) -> str:
