@@ -14,7 +14,9 @@
 //   kp_schur       one wave per lower 9x9 block of a partition's reduced
 //                  camera system S = H_cc + mu diag - sum (H_cl W) H_cl^T,
 //                  summed in a fixed order over a pair list built at create;
-//   kp_chol_*      blocked right-looking Cholesky of every S (64x64 tiles);
+//   kp_chol_*      blocked right-looking Cholesky of every S (64x64 tiles):
+//                  per step a panel solve and a trailing update, whose block
+//                  for the next diagonal tile factors it in the same launch;
 //   kp_trsv        L L^T dc = b per partition;
 //   kp_step        dl = -W (g_l + sum H_cl^T dc) per landmark; retraction
 //                  R Exp(dtheta), t + dt, d + dd, l + dl;
@@ -87,6 +89,7 @@ struct PP {
     double *vc, *vl, *Hcl;
     double *Hcc, *gc, *W, *Wg;
     double *Smat, *vec;
+    double* dinv;                      // 1 / L_rr of each factor, laid out like vec
     double* ps;
     double* trace;
     int* flag;
@@ -751,240 +754,331 @@ __device__ __forceinline__ double lane_value(double x, int j) {
     return __builtin_bit_cast(double, o);
 }
 
-typedef __attribute__((address_space(3))) double lds_double;
-
-// LDS accesses of the diagonal factorisation as volatile asm statements:
-// they keep their program order among themselves (which is all the ordering
-// the column exchange needs), and every read waits for its data inside the
-// statement, so no result is used early and no read is hoisted.  No memory
-// clobber: the row held in registers must stay in registers.
-// lds_read8: eight doubles at LDS byte address addr (the same for every lane:
-// a broadcast).
-__device__ __forceinline__ void lds_read8(unsigned addr, double* v) {
-    asm volatile(
-        "ds_read_b64 %0, %8\n\t"
-        "ds_read_b64 %1, %8 offset:8\n\t"
-        "ds_read_b64 %2, %8 offset:16\n\t"
-        "ds_read_b64 %3, %8 offset:24\n\t"
-        "ds_read_b64 %4, %8 offset:32\n\t"
-        "ds_read_b64 %5, %8 offset:40\n\t"
-        "ds_read_b64 %6, %8 offset:48\n\t"
-        "ds_read_b64 %7, %8 offset:56\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]), "=&v"(v[7])
-        : "v"(addr));
+// 1/sqrt(d) for a normal d > 0: the hardware reciprocal square root refined
+// by two coupled Newton steps on g ~ sqrt(d), h ~ 1/(2 sqrt(d)), each of
+// which squares the relative error.  A few ulp, with no division or
+// square-root sequence on the factorisation's serial chain.
+__device__ __forceinline__ double rsqrt_refined(double d) {
+    const double y = __builtin_amdgcn_rsq(d);
+    double g = d * y, h = 0.5 * y;
+    double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    e = fma(-g, h, 0.5);
+    h = fma(h, e, h);
+    return 2.0 * h;
 }
 
-__device__ __forceinline__ double lds_read1(unsigned addr) {
-    double v;
-    asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(v) : "v"(addr));
-    return v;
-}
+constexpr int kPW = 16;          // tile columns per wave in the four-wave tile kernels
+constexpr int kNW = kNB / kPW;   // waves of those kernels
+constexpr int kLD = kNB + 2;     // LDS row stride of a staged tile: 16-byte aligned rows, read in pairs
 
-__device__ __forceinline__ void lds_write1(unsigned addr, double v) {
-    asm volatile("ds_write_b64 %0, %1" : : "v"(addr), "v"(v));
-}
-
-// x_jj -= rc * (eight doubles at LDS byte address addr), reads and updates in
-// one statement, so that no read result outlives its update.
-__device__ __forceinline__ void lds_fnma8(unsigned addr, double rc, double& x0, double& x1, double& x2,
-                                          double& x3, double& x4, double& x5, double& x6, double& x7) {
-    double t0, t1, t2, t3, t4, t5, t6, t7;
-    asm volatile(
-        "ds_read_b64 %8, %16\n\t"
-        "ds_read_b64 %9, %16 offset:8\n\t"
-        "ds_read_b64 %10, %16 offset:16\n\t"
-        "ds_read_b64 %11, %16 offset:24\n\t"
-        "ds_read_b64 %12, %16 offset:32\n\t"
-        "ds_read_b64 %13, %16 offset:40\n\t"
-        "ds_read_b64 %14, %16 offset:48\n\t"
-        "ds_read_b64 %15, %16 offset:56\n\t"
-        "s_waitcnt lgkmcnt(0)\n\t"
-        "v_fma_f64 %0, -%17, %8, %0\n\t"
-        "v_fma_f64 %1, -%17, %9, %1\n\t"
-        "v_fma_f64 %2, -%17, %10, %2\n\t"
-        "v_fma_f64 %3, -%17, %11, %3\n\t"
-        "v_fma_f64 %4, -%17, %12, %4\n\t"
-        "v_fma_f64 %5, -%17, %13, %5\n\t"
-        "v_fma_f64 %6, -%17, %14, %6\n\t"
-        "v_fma_f64 %7, -%17, %15, %7"
-        : "+v"(x0), "+v"(x1), "+v"(x2), "+v"(x3), "+v"(x4), "+v"(x5), "+v"(x6), "+v"(x7),
-          "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(t4), "=&v"(t5), "=&v"(t6), "=&v"(t7)
-        : "v"(addr), "v"(rc));
-}
-
-// Two groups of eight in one statement: the second group's reads are in
-// flight while the first group's updates run (lgkmcnt(8) waits for the
-// oldest eight reads only).
-__device__ __forceinline__ void lds_fnma16(unsigned addr, double rc, double* x) {
-    double t0, t1, t2, t3, t4, t5, t6, t7, u0, u1, u2, u3, u4, u5, u6, u7;
-    asm volatile(
-        "ds_read_b64 %16, %32\n\t"
-        "ds_read_b64 %17, %32 offset:8\n\t"
-        "ds_read_b64 %18, %32 offset:16\n\t"
-        "ds_read_b64 %19, %32 offset:24\n\t"
-        "ds_read_b64 %20, %32 offset:32\n\t"
-        "ds_read_b64 %21, %32 offset:40\n\t"
-        "ds_read_b64 %22, %32 offset:48\n\t"
-        "ds_read_b64 %23, %32 offset:56\n\t"
-        "ds_read_b64 %24, %32 offset:64\n\t"
-        "ds_read_b64 %25, %32 offset:72\n\t"
-        "ds_read_b64 %26, %32 offset:80\n\t"
-        "ds_read_b64 %27, %32 offset:88\n\t"
-        "ds_read_b64 %28, %32 offset:96\n\t"
-        "ds_read_b64 %29, %32 offset:104\n\t"
-        "ds_read_b64 %30, %32 offset:112\n\t"
-        "ds_read_b64 %31, %32 offset:120\n\t"
-        "s_waitcnt lgkmcnt(8)\n\t"
-        "v_fma_f64 %0, -%33, %16, %0\n\t"
-        "v_fma_f64 %1, -%33, %17, %1\n\t"
-        "v_fma_f64 %2, -%33, %18, %2\n\t"
-        "v_fma_f64 %3, -%33, %19, %3\n\t"
-        "v_fma_f64 %4, -%33, %20, %4\n\t"
-        "v_fma_f64 %5, -%33, %21, %5\n\t"
-        "v_fma_f64 %6, -%33, %22, %6\n\t"
-        "v_fma_f64 %7, -%33, %23, %7\n\t"
-        "s_waitcnt lgkmcnt(0)\n\t"
-        "v_fma_f64 %8, -%33, %24, %8\n\t"
-        "v_fma_f64 %9, -%33, %25, %9\n\t"
-        "v_fma_f64 %10, -%33, %26, %10\n\t"
-        "v_fma_f64 %11, -%33, %27, %11\n\t"
-        "v_fma_f64 %12, -%33, %28, %12\n\t"
-        "v_fma_f64 %13, -%33, %29, %13\n\t"
-        "v_fma_f64 %14, -%33, %30, %14\n\t"
-        "v_fma_f64 %15, -%33, %31, %15"
-        : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
-          "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]), "+v"(x[14]), "+v"(x[15]),
-          "=&v"(t0), "=&v"(t1), "=&v"(t2), "=&v"(t3), "=&v"(t4), "=&v"(t5), "=&v"(t6), "=&v"(t7),
-          "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3), "=&v"(u4), "=&v"(u5), "=&v"(u6), "=&v"(u7)
-        : "v"(addr), "v"(rc));
-}
-
-// Column C of the diagonal factorisation (compile-time recursion, so that
-// every index into the row is a constant and the row stays in registers).
-template <int C>
-__device__ __forceinline__ void chol_column(double (&row)[kNB], int r, unsigned cbase, bool& bad) {
-    lds_write1(cbase + 8 * r, row[C]);
-    const double d = lds_read1(cbase + 8 * C);
-    bad = bad || !(d > 0.0);
-    const double l = d > 0.0 ? sqrt(d) : 1.0;
-    row[C] = r > C ? row[C] / l : (r == C ? l : row[C]);
-    lds_write1(cbase + 8 * r, row[C]);
-    constexpr int g0 = (C + 1) / 8;  // the group holding column C + 1
-    if constexpr (g0 < kNB / 8) {
-        if constexpr ((C + 1) % 8 != 0) {  // partly left of the pivot: masked
-            double L[8];
-            lds_read8(cbase + 64 * g0, L);
+// n consecutive doubles at a 16-byte aligned LDS address, read as pairs.
+template <int N>
+__device__ __forceinline__ void lds_pairs(const double* src, double* v) {
+    static_assert(N % 2 == 0, "pairs");
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj)
-                if (8 * g0 + jj > C) row[8 * g0 + jj] -= row[C] * L[jj];
+    for (int c = 0; c < N; c += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(src + c);
+        v[c] = t.x;
+        v[c + 1] = t.y;
+    }
+}
+
+// A copy of v that the compiler takes as varying across lanes, so that
+// address arithmetic scaled by it stays in vector registers instead of
+// being hoisted into dozens of scalar registers (one ds_bpermute).
+__device__ __forceinline__ int varying(int v) { return __shfl(v, threadIdx.x & 63, kW); }
+
+// Panel P of a diagonal tile's factorisation, run by wave P, whose lane r
+// holds x[i] = entry (r, 16P + i) of the tile after the earlier panels'
+// updates.  Column C = 16P + i: the pivot from lane C by readlane; every
+// lane scales its entry by 1/sqrt(pivot) (L_rC below the diagonal,
+// A_CC / sqrt(A_CC) = L_CC on it); the panel's later columns j take
+// L_rC L_jC, with L_(C+1)C (on the pivot chain) read from lane C + 1 and the
+// others broadcast from col (LDS).  The right-hand side rides along as one
+// more column: y_C = b_C / L_CC, then b_r -= L_rC y_C.  Lane C keeps y_C
+// and 1/L_CC.  The updates need no per-lane select: lanes above the
+// diagonal carry values of the upper triangle, which are never stored or
+// read.  The previous panel's rank-16 update (in T, row stride kLD) reaches
+// each column just before its pivot, so that its products fill the pivot
+// chain's idle issue slots.
+template <int P>
+__device__ __forceinline__ void factor_panel(double (&x)[kPW], const double (*T)[kLD], double* col, double& yb,
+                                             double& yfin, double& invfin, int r, bool& bad) {
+    double a[kPW];  // this row's entries in the previous panel
+    if constexpr (P > 0) lds_pairs<kPW>(T[r] + kPW * (P - 1), a);
+#pragma unroll
+    for (int i = 0; i < kPW; ++i) {
+        const int C = kPW * P + i;
+        if constexpr (P > 0) {
+            double l[kPW];
+            lds_pairs<kPW>(T[C] + kPW * (P - 1), l);
+            double s0 = x[i], s1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < kPW; c += 2) {
+                s0 = fma(-a[c], l[c], s0);
+                s1 = fma(-a[c + 1], l[c + 1], s1);
+            }
+            x[i] = s0 + s1;
         }
-        constexpr int gfull = (C + 1) % 8 != 0 ? g0 + 1 : g0;
-        constexpr int npair = (kNB / 8 - gfull) / 2;
+        const double d = lane_value(x[i], C);
+        bad = bad || !(d > 0.0);
+        const double inv = rsqrt_refined(d > 0.0 ? d : 1.0);
+        x[i] *= inv;
+        const double yc = lane_value(yb, C) * inv;
+        if (r == C) {
+            yfin = yc;
+            invfin = inv;
+        }
+        yb = fma(-x[i], yc, yb);
+        if (i + 1 < kPW) {
+            x[i + 1] = fma(-x[i], lane_value(x[i], C + 1), x[i + 1]);
+            if (i + 2 < kPW) {
+                col[r] = x[i];
+                const int j0 = (i + 2) & ~1;  // pairs from an even column; column i + 1 is masked out
+                double v[kPW];
 #pragma unroll
-        for (int u = 0; u < npair; ++u)  // full groups two at a time
-            lds_fnma16(cbase + 64 * (gfull + 2 * u), row[C], &row[8 * (gfull + 2 * u)]);
-        if constexpr ((kNB / 8 - gfull) % 2 != 0) {
-            constexpr int g = kNB / 8 - 1;
-            lds_fnma8(cbase + 64 * g, row[C], row[8 * g], row[8 * g + 1], row[8 * g + 2], row[8 * g + 3],
-                      row[8 * g + 4], row[8 * g + 5], row[8 * g + 6], row[8 * g + 7]);
+                for (int j = j0; j < kPW; j += 2) {
+                    const double2 t = *reinterpret_cast<const double2*>(col + kPW * P + j);
+                    v[j] = t.x;
+                    v[j + 1] = t.y;
+                }
+#pragma unroll
+                for (int j = i + 2; j < kPW; ++j) x[j] = fma(-x[i], v[j], x[j]);
+            }
         }
     }
-    if constexpr (C + 1 < kNB) chol_column<C + 1>(row, r, cbase, bad);
 }
 
-// Blocked right-looking Cholesky, step k: factor the diagonal tile with one
-// wave, lane r holding row r in registers.  Column c: every lane publishes
-// A_rc in LDS and reads the pivot; the rows below scale to L_rc and publish
-// it; every lane then takes L_rc L_jc out of A_rj (j > c), reading L_jc by
-// broadcast, eight at a time.  A wave's LDS accesses complete in program
-// order, so no barrier is needed.  Lanes above the diagonal (r < j) update
-// entries of the upper triangle, which start at zero and are never stored,
-// so the update needs no mask.  The 64 loads of a row are issued together.
-__global__ __launch_bounds__(64) void kp_chol_diag(PP p, int k) {
-    __shared__ double col[kNB];
-    const int a = blockIdx.x;
-    double* q = p.ps + (size_t)a * kPS;
-    if (q[P_ACTIVE] == 0.0 || k >= p.nt[a]) return;
-    const int np = p.npad[a];
-    double* Sr = p.Smat + p.soff[a] + (size_t)(kNB * k + threadIdx.x) * np + kNB * k;
-    const int r = threadIdx.x;
-    const unsigned cbase = (unsigned)(size_t)(lds_double*)col;
+// Rank-16 update of wave w's columns by panel P (w > P):
+// x[i] -= sum_c M_(r, 16P+c) M_(16w+i, 16P+c), M a tile in LDS (row stride
+// kLD): the lane's own row, and the rows of the wave's columns by broadcast,
+// in pairs.
+template <int P>
+__device__ __forceinline__ void panel_update(double (&x)[kPW], const double (*M)[kLD], int r, int w) {
+    double a[kPW];
+    lds_pairs<kPW>(M[r] + kPW * P, a);
+#pragma unroll
+    for (int i = 0; i < kPW; ++i) {
+        double l[kPW];
+        lds_pairs<kPW>(M[kPW * w + i] + kPW * P, l);
+        double s0 = x[i], s1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kPW; c += 2) {
+            s0 = fma(-a[c], l[c], s0);
+            s1 = fma(-a[c + 1], l[c + 1], s1);
+        }
+        x[i] = s0 + s1;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void factor_panels(double (&x)[kPW], double (*T)[kLD], double* ybuf, double& yb,
+                                              double& yfin, double& invfin, int r, int w, bool& bad) {
+    if (w == P) {
+        if constexpr (P > 0) yb = ybuf[r];
+        factor_panel<P>(x, T, ybuf + kNB, yb, yfin, invfin, r, bad);
+#pragma unroll
+        for (int c = 0; c < kPW; ++c) T[r][kPW * P + c] = x[c];
+        ybuf[r] = yb;
+    }
+    __syncthreads();
+    if constexpr (P + 1 < kNW) {
+        if (w > P + 1) panel_update<P>(x, T, r, w);  // wave P + 1 takes it column by column
+        factor_panels<P + 1>(x, T, ybuf, yb, yfin, invfin, r, w, bad);
+    }
+}
+
+// Blocked right-looking Cholesky: factor diagonal tile k of partition a,
+// which T (LDS, row-major, stride kLD) holds after every earlier step's
+// update, with the block's four waves, wave w holding columns 16w .. 16w+15
+// of every row (lane r: row r).  Panel P is factored by wave P and published
+// in T; after a barrier the waves to its right take its rank-16 update.
+// Stores L_kk (lower triangle, coalesced from T), 1/L_rr, and the forward
+// substitution folded into the factorisation: y_k = L_kk^-1 b_k, b_k already
+// reduced by the earlier panels, which then take L_ik y_k out of b_i for the
+// tiles below.  Every thread of the 256-thread block calls it, with bv =
+// entry (threadIdx.x mod 64) of b_k, loaded early by the caller, and ybuf
+// 128 doubles of LDS (16-byte aligned).
+__device__ __forceinline__ void factor_tile(const PP& p, int a, int k, double (*T)[kLD], double* ybuf,
+                                            double bv) {
+    const int r = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double x[kPW];
+#pragma unroll
+    for (int i = 0; i < kPW; ++i) {
+        const double v = T[r][kPW * w + i];
+        x[i] = kPW * w + i <= r ? v : 0.0;
+    }
     double* bk = p.vec + p.voff[a] + kNB * k;
-    double y = bk[r];  // right-hand side entry r of this tile, reduced by the earlier tiles
-    double row[kNB];
-#pragma unroll
-    for (int m = 0; m < kNB; ++m) row[m] = Sr[m];
-#pragma unroll
-    for (int m = 0; m < kNB; ++m) row[m] = m <= r ? row[m] : 0.0;
+    double yb = w == 0 ? bv : 0.0, yfin = 0.0, invfin = 1.0;
     bool bad = false;
-    chol_column<0>(row, r, cbase, bad);
-    if (r == 0 && bad) q[P_OK] = 0.0;
-#pragma unroll
-    for (int m = 0; m < kNB; ++m)
-        if (m <= r) Sr[m] = row[m];
-    // forward substitution folded into the factorisation: L_kk y = b_k here,
-    // and the panel step takes L_ik y_k out of b_i for the tiles below
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-        if (r == c) lds_write1(cbase, y / row[c]);
-        const double yc = lds_read1(cbase);
-        y = r == c ? yc : (r > c ? y - row[c] * yc : y);
+    factor_panels<0>(x, T, ybuf, yb, yfin, invfin, r, w, bad);
+    if (r == 0 && bad) p.ps[(size_t)a * kPS + P_OK] = 0.0;
+    if ((r >> 4) == w) {  // rows of the wave's own panel: their y and 1/L_rr
+        p.dinv[p.voff[a] + kNB * k + r] = invfin;
+        bk[r] = yfin;
     }
-    bk[r] = y;
+    const int np = p.npad[a];
+    double* S = p.Smat + p.soff[a] + (size_t)(kNB * k) * np + kNB * k;
+#pragma unroll
+    for (int i = 0; i < kPW; ++i) {  // wave w stores rows 16w .. 16w+15, lane r column r
+        const int rr = kPW * w + i;
+        if (r <= rr) S[(size_t)rr * np + r] = T[rr][r];
+    }
 }
 
-// Step k: L_ik = A_ik L_kk^-T for every tile row i > k.  Lane r solves row r
-// of the tile, x L_kk^T = a, by forward substitution in registers; L_kk is
-// staged in LDS and read by broadcast.
-__global__ __launch_bounds__(64) void kp_chol_trsm(PP p, int k) {
-    __shared__ double L[kNB][kNB + 1];
-    __shared__ double yk[kNB];
+// The first diagonal tile of every partition (each later one is factored by
+// the update launch that completes it).
+__global__ __launch_bounds__(256) void kp_chol_diag(PP p, int k) {
+    __shared__ __align__(16) double T[kNB][kLD];
+    __shared__ __align__(16) double ybuf[2 * kNB];
+    const int a = blockIdx.x;
+    if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0 || k >= p.nt[a]) return;
+    const int np = p.npad[a];
+    const double* S = p.Smat + p.soff[a] + (size_t)(kNB * k) * np + kNB * k;
+    const int tid = threadIdx.x;
+    const double bv = p.vec[p.voff[a] + kNB * k + (tid & 63)];
+    double v[kNB * kNB / 256];
+#pragma unroll
+    for (int u = 0; u < kNB * kNB / 256; ++u) {
+        const int e = tid + 256 * u;
+        v[u] = S[(size_t)(e / kNB) * np + e % kNB];
+    }
+#pragma unroll
+    for (int u = 0; u < kNB * kNB / 256; ++u) {
+        const int e = tid + 256 * u;
+        T[e / kNB][e % kNB] = v[u];
+    }
+    __syncthreads();
+    factor_tile(p, a, k, T, ybuf, bv);
+}
+
+// Panel P of a panel tile's triangular solve x L_kk^T = a (wave P; lane r:
+// row r): x_C = a_C / L_CC, then x_C L_jC leaves a_j for the panel's later
+// columns j; the panel is published in X, and after a barrier the waves to
+// its right take its rank-16 update (the next wave column by column, just
+// before each division, the others at once).
+template <int P>
+__device__ __forceinline__ void trsm_panels(double (&x)[kPW], const double (*Lk)[kLD], double (*X)[kLD],
+                                            const double* iv, int r, int w) {
+    if (w == P) {
+        double s[kPW];  // this row's solved entries in the previous panel
+        if constexpr (P > 0) lds_pairs<kPW>(X[r] + kPW * (P - 1), s);
+#pragma unroll
+        for (int i = 0; i < kPW; ++i) {
+            const int C = kPW * P + i;
+            if constexpr (P > 0) {  // the previous panel's update, column by column
+                double l[kPW];
+                lds_pairs<kPW>(Lk[C] + kPW * (P - 1), l);
+                double t0 = x[i], t1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < kPW; c += 2) {
+                    t0 = fma(-s[c], l[c], t0);
+                    t1 = fma(-s[c + 1], l[c + 1], t1);
+                }
+                x[i] = t0 + t1;
+            }
+            x[i] *= iv[C];
+#pragma unroll
+            for (int j = i + 1; j < kPW; ++j) x[j] = fma(-x[i], Lk[kPW * P + j][C], x[j]);
+        }
+#pragma unroll
+        for (int c = 0; c < kPW; ++c) X[r][kPW * P + c] = x[c];
+    }
+    __syncthreads();
+    if constexpr (P + 1 < kNW) {
+        if (w > P + 1) {  // x[i] -= sum_c X_(r, 16P+c) L_(16w+i, 16P+c); wave P + 1 takes it column by column
+            double s[kPW];
+            lds_pairs<kPW>(X[r] + kPW * P, s);
+#pragma unroll
+            for (int i = 0; i < kPW; ++i) {
+                double l[kPW];
+                lds_pairs<kPW>(Lk[kPW * w + i] + kPW * P, l);
+                double t0 = x[i], t1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < kPW; c += 2) {
+                    t0 = fma(-s[c], l[c], t0);
+                    t1 = fma(-s[c + 1], l[c + 1], t1);
+                }
+                x[i] = t0 + t1;
+            }
+        }
+        trsm_panels<P + 1>(x, Lk, X, iv, r, w);
+    }
+}
+
+// Step k: L_ik = A_ik L_kk^-T for every tile row i > k, one block of four
+// waves per tile (wave w: columns 16w .. 16w+15, lane r: row r), blocked
+// over panels like the factorisation, with the stored reciprocals of
+// L_kk's diagonal; then b_i -= L_ik y_k.
+__global__ __launch_bounds__(256) void kp_chol_trsm(PP p, int k) {
+    __shared__ __align__(16) double Lk[kNB][kLD];
+    __shared__ __align__(16) double X[kNB][kLD];
+    __shared__ double yk[kNB], iv[kNB];
     const int a = blockIdx.y;
     const int i = k + 1 + blockIdx.x;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0 || i >= p.nt[a]) return;
     const int np = p.npad[a];
+    const int tid = threadIdx.x, r = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double* Lkk = p.Smat + p.soff[a] + (size_t)(kNB * k) * np + kNB * k;
-    double* Ar = p.Smat + p.soff[a] + (size_t)(kNB * i + threadIdx.x) * np + kNB * k;
-    const int t = threadIdx.x;
-    double x[kNB];
-#pragma unroll
-    for (int m = 0; m < kNB; ++m) x[m] = Ar[m];
-    {
-        double col[kNB];
-#pragma unroll
-        for (int rr = 0; rr < kNB; ++rr) col[rr] = Lkk[(size_t)rr * np + t];
-#pragma unroll
-        for (int rr = 0; rr < kNB; ++rr) L[rr][t] = col[rr];
-    }
+    double2* Ar = reinterpret_cast<double2*>(p.Smat + p.soff[a] + (size_t)(kNB * i + r) * np + kNB * k + kPW * w);
     double* b = p.vec + p.voff[a];
-    yk[t] = b[kNB * k + t];  // y_k, solved by the diagonal step
+    // every global load in flight before the first wait
+    double x[kPW];
+#pragma unroll
+    for (int m = 0; m < kPW / 2; ++m) {
+        const double2 v = Ar[m];
+        x[2 * m] = v.x;
+        x[2 * m + 1] = v.y;
+    }
+    double v[kNB * kNB / 256];
+#pragma unroll
+    for (int u = 0; u < kNB * kNB / 256; ++u) {
+        const int e = tid + 256 * u;
+        v[u] = Lkk[(size_t)(e / kNB) * np + e % kNB];
+    }
+    const double ykr = b[kNB * k + r];  // y_k, solved by the diagonal step
+    const double ivr = p.dinv[p.voff[a] + kNB * k + r];
+    const double bir = b[kNB * i + r];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kNB * kNB / 256; ++u) {
+        const int e = tid + 256 * u;
+        Lk[e / kNB][e % kNB] = v[u];
+    }
+    if (w == 0) {
+        yk[r] = ykr;
+        iv[r] = ivr;
+    }
     __syncthreads();
+    trsm_panels<0>(x, Lk, X, iv, r, w);
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-        double s = x[c];
+    for (int m = 0; m < kPW / 2; ++m) Ar[m] = make_double2(x[2 * m], x[2 * m + 1]);
+    if (w == 0) {  // forward substitution of the right-hand side: b_i -= L_ik y_k
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int m = 0; m < c; ++m) s -= x[m] * L[c][m];
-        x[c] = s / L[c][c];
+        for (int c = 0; c < kNB; c += 2) {
+            s0 += X[r][c] * yk[c];
+            s1 += X[r][c + 1] * yk[c + 1];
+        }
+        b[kNB * i + r] = bir - (s0 + s1);
     }
-#pragma unroll
-    for (int m = 0; m < kNB; ++m) Ar[m] = x[m];
-    // forward substitution of the right-hand side: b_i -= L_ik y_k
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int c = 0; c < kNB; c += 2) {
-        s0 += x[c] * yk[c];
-        s1 += x[c + 1] * yk[c + 1];
-    }
-    b[kNB * i + t] -= s0 + s1;
 }
 
 // Step k: A_ij -= L_ik L_jk^T for tiles k < j <= i; the inner dimension in
-// two halves of 32 columns (34 KB of LDS).
-__global__ __launch_bounds__(256) void kp_chol_update(PP p, int k) {
+// two halves of 32 columns (34 KB of LDS).  The block of tile (k+1, k+1),
+// whose update is the last one it receives, completes it in LDS and
+// factors it for step k + 1 while the other tiles update.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kp_chol_update(PP p, int k) {
     constexpr int kH = kNB / 2;
-    __shared__ double Li[kNB][kH + 1];
-    __shared__ double Lj[kNB][kH + 1];
+    __shared__ __align__(16) double sh[2 * kNB * (kH + 1)];
+    __shared__ __align__(16) double ybuf[2 * kNB];
+    static_assert(kNB * kLD <= 2 * kNB * (kH + 1), "tile buffer");
+    double (*Li)[kH + 1] = reinterpret_cast<double (*)[kH + 1]>(sh);
+    double (*Lj)[kH + 1] = reinterpret_cast<double (*)[kH + 1]>(sh + kNB * (kH + 1));
     const int a = blockIdx.y;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0) return;
     const int m = p.nt[a] - k - 1;  // trailing tiles
@@ -999,6 +1093,9 @@ __global__ __launch_bounds__(256) void kp_chol_update(PP p, int k) {
     const double* base = p.Smat + p.soff[a];
     const int tid = threadIdx.x;
     const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
+    double* Aij = p.Smat + p.soff[a] + (size_t)(kNB * i) * np + kNB * j;
+    // tile (k+1, k+1) is factored after its update: its b entry now
+    const double bv = t == 0 ? p.vec[p.voff[a] + kNB * (k + 1) + (tid & 63)] : 0.0;
     double acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -1032,71 +1129,119 @@ __global__ __launch_bounds__(256) void kp_chol_update(PP p, int k) {
                 for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
         }
     }
-    double* Aij = p.Smat + p.soff[a] + (size_t)(kNB * i) * np + kNB * j;
+    if (t == 0) {  // tile (k+1, k+1): complete it in LDS and factor it
+        double (*T)[kLD] = reinterpret_cast<double (*)[kLD]>(sh);
+        __syncthreads();  // every wave is done with Li and Lj
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[r0 + u][c0 + v] = Aij[(size_t)(r0 + u) * np + c0 + v] - acc[u][v];
+        __syncthreads();
+        factor_tile(p, a, k + 1, T, ybuf, bv);
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) Aij[(size_t)(r0 + u) * np + c0 + v] -= acc[u][v];
 }
 
+// Stages the strictly lower part of diagonal tile c0 / 64 in D (LDS, only
+// wave 0's), every row's load in flight at once.
+__device__ __forceinline__ void trsv_stage(const double* L, int np, int c0, double (*D)[kNB + 1]) {
+    const int lane = threadIdx.x & 63;
+    const int npv = varying(np);
+    const double* q = L + (size_t)c0 * npv + c0 + lane;
+    double v[kNB];  // loaded by every lane: a select below, not a branch around a load
+#pragma unroll
+    for (int rr = 0; rr < kNB; ++rr) {
+        v[rr] = *q;
+        q += npv;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every load issued before the first wait
+#pragma unroll
+    for (int rr = 0; rr < kNB; ++rr) D[rr][lane] = lane < rr ? v[rr] : 0.0;
+}
+
+// Dot of tile c0 / 64's rows of L, column r, with x of that tile:
+// sum_c L_(c0+c, r) x_c.  Every load is issued before the first use.
+__device__ __forceinline__ double trsv_dot(const double* L, int npv, int c0, int r, const double* xk) {
+    const double* q = L + (size_t)c0 * npv + r;
+    double v[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) {
+        v[c] = *q;
+        q += npv;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kNB; c += 2) {
+        s0 = fma(v[c], xk[c], s0);
+        s1 = fma(v[c + 1], xk[c + 1], s1);
+    }
+    return s0 + s1;
+}
+
+// Backward sweep of a staged diagonal tile for wave 0 (lane = row c0 +
+// lane, y its right-hand side entry reduced by every later tile), with L^T,
+// (L^T)_(lane, c) = L_(c, lane), and the stored reciprocals of the
+// diagonal: lane c's entry is final at step c.
+__device__ __forceinline__ double trsv_solve(const double (*D)[kNB + 1], const double* dinv, int c0, double y) {
+    const int lane = threadIdx.x & 63;
+    const double iv = dinv[c0 + lane];
+    double xv = y;
+#pragma unroll
+    for (int c = kNB - 1; c >= 0; --c) xv = fma(-D[c][lane], lane_value(xv * iv, c), xv);
+    return xv * iv;
+}
+
 // L^T x = y in place on the partition's vector (the forward half, L y = b,
 // is folded into the factorisation), one 64-row tile at a time from the
-// last: solve the tile's triangle in registers (one wave, lane = row), then
-// take the solved values out of the rows above (one lane per row, reading
-// the tile's rows of L, consecutive across lanes).
-__global__ __launch_bounds__(256) void kp_trsv(PP p) {
-    __shared__ double xs[kNB];
-    __shared__ double D[kNB][kNB + 1];  // the current diagonal tile
+// last, with look-ahead: once x of tile kt is known, wave 0 takes it out of
+// the rows of tile kt - 1 and solves that tile's triangle; wave 1 stages
+// the diagonal tile wave 0 needs next; the other waves take x of tile kt out
+// of the rows above (one thread per row, reading tile kt's rows of L,
+// consecutive across lanes).
+__global__ __launch_bounds__(512) void kp_trsv(PP p) {
+    constexpr int kT = 512;
+    __shared__ double xs[2][kNB];
+    __shared__ double D[2][kNB][kNB + 1];  // diagonal tiles kt and kt - 1
     const int a = blockIdx.x;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0) return;
     const int np = p.npad[a], nt = p.nt[a];
+    if (nt == 0) return;
     const double* L = p.Smat + p.soff[a];
     double* b = p.vec + p.voff[a];
-    const int tid = threadIdx.x;
-    for (int kt = nt - 1; kt >= 0; --kt) {
+    const double* dinv = p.dinv + p.voff[a];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int npv = varying(np);
+    if (wave == 0) {
+        const int c0 = kNB * (nt - 1);
+        const double y = b[c0 + lane];
+        trsv_stage(L, np, c0, D[(nt - 1) & 1]);
+        const double x = trsv_solve(D[(nt - 1) & 1], dinv, c0, y);
+        xs[(nt - 1) & 1][lane] = x;
+        b[c0 + lane] = x;
+    } else if (wave == 1 && nt >= 2) {
+        trsv_stage(L, np, kNB * (nt - 2), D[(nt - 2) & 1]);
+    }
+    for (int kt = nt - 1; kt >= 1; --kt) {
+        __syncthreads();  // x of tile kt is in xs[kt & 1], diagonal tile kt - 1 in D[(kt - 1) & 1]
         const int c0 = kNB * kt;
-        if (tid < kNB) xs[tid] = b[c0 + tid];
-        {
-            double v[kNB * kNB / 256];
-#pragma unroll
-            for (int u = 0; u < kNB * kNB / 256; ++u) {
-                const int e = tid + 256 * u;
-                v[u] = L[(size_t)(c0 + e / kNB) * np + c0 + e % kNB];
-            }
-#pragma unroll
-            for (int u = 0; u < kNB * kNB / 256; ++u) {
-                const int e = tid + 256 * u;
-                D[e / kNB][e % kNB] = v[u];
-            }
+        const double* xk = xs[kt & 1];
+        if (wave == 0) {
+            const int r = c0 - kNB + lane;
+            const double y = b[r];
+            const double x = trsv_solve(D[(kt - 1) & 1], dinv, c0 - kNB, y - trsv_dot(L, npv, c0, r, xk));
+            xs[(kt - 1) & 1][lane] = x;
+            b[r] = x;
+        } else if (wave == 1) {
+            if (kt >= 2) trsv_stage(L, np, c0 - 2 * kNB, D[kt & 1]);  // tile kt's buffer is free now
+        } else {
+            for (int r = tid - 2 * kW; r < c0 - kNB; r += kT - 2 * kW) b[r] -= trsv_dot(L, npv, c0, r, xk);
         }
-        __syncthreads();
-        if (tid < kNB) {  // backward sweep with L^T: (L^T)_(tid, c) = L_(c, tid)
-            double xv = xs[tid];
-            double dcol[kNB];
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) dcol[c] = D[c][tid];
-#pragma unroll
-            for (int c = kNB - 1; c >= 0; --c) {
-                const double xc = lane_value(xv, c) / lane_value(dcol[c], c);
-                xv = tid == c ? xc : (tid < c ? xv - dcol[c] * xc : xv);
-            }
-            xs[tid] = xv;
-            b[c0 + tid] = xv;
-        }
-        __syncthreads();
-        for (int r = tid; r < c0; r += 256) {
-            double v[kNB];
-#pragma unroll
-            for (int c = 0; c < kNB; ++c) v[c] = L[(size_t)(c0 + c) * np + r];
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int c = 0; c < kNB; c += 2) {
-                s0 += v[c] * xs[c];
-                s1 += v[c + 1] * xs[c + 1];
-            }
-            b[r] -= s0 + s1;
-        }
-        __syncthreads();
     }
 }
 
@@ -1541,6 +1686,7 @@ void carve(const PLayout& L, Carve& c, PP& p, Bufs& b) {
     p.Wg = c.take<double>(kLS * N);
     p.Smat = c.take<double>((size_t)L.smat_total);
     p.vec = c.take<double>((size_t)L.vec_total);
+    p.dinv = c.take<double>((size_t)L.vec_total);
     p.ps = c.take<double>((size_t)L.S * kPS);
     p.trace = c.take<double>(kTraceCap);
     p.flag = c.take<int>(64);
@@ -1659,21 +1805,21 @@ bool lm_all(daba_part_handle* h, const double* yc, const double* yl, double* oc,
         }
         {
             Timed t(h, C_CHOL);
-            for (int k = 0; k < ntmax; ++k) {
-                hipLaunchKernelGGL(kp_chol_diag, dim3(p.S), dim3(64), 0, h->stream, p, k);
+            // the first diagonal tile; each later one is factored by the
+            // update launch that completes it
+            hipLaunchKernelGGL(kp_chol_diag, dim3(p.S), dim3(256), 0, h->stream, p, 0);
+            h->chol_launches += 1;
+            for (int k = 0; k + 1 < ntmax; ++k) {
                 const int m = ntmax - k - 1;
-                if (m > 0) {
-                    hipLaunchKernelGGL(kp_chol_trsm, dim3(m, p.S), dim3(64), 0, h->stream, p, k);
-                    hipLaunchKernelGGL(kp_chol_update, dim3(m * (m + 1) / 2, p.S), dim3(256), 0, h->stream, p, k);
-                    h->chol_launches += 2;
-                }
-                h->chol_launches += 1;
+                hipLaunchKernelGGL(kp_chol_trsm, dim3(m, p.S), dim3(256), 0, h->stream, p, k);
+                hipLaunchKernelGGL(kp_chol_update, dim3(m * (m + 1) / 2, p.S), dim3(256), 0, h->stream, p, k);
+                h->chol_launches += 2;
             }
             hipck(hipGetLastError(), "Cholesky");
         }
         {
             Timed t(h, C_SOLVE);
-            hipLaunchKernelGGL(kp_trsv, dim3(p.S), dim3(256), 0, h->stream, p);
+            hipLaunchKernelGGL(kp_trsv, dim3(p.S), dim3(512), 0, h->stream, p);
             hipLaunchKernelGGL(kp_step, dim3(ge), dim3(64), 0, h->stream, p, b.cur_c, b.cur_l, b.try_c, b.try_l);
             hipck(hipGetLastError(), "solve");
         }
