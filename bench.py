@@ -254,12 +254,14 @@ def bench_partition(args, prob, S):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     groups = sol.iterate_timed(steps)
-    # reduced camera systems: one per partition, order 9 M_a, padded to 64
+    # reduced camera systems: one per partition, order 9 M_a (the kernels
+    # factor it padded to a multiple of 64; the flops counted are those of
+    # the unpadded order)
     cam_part = np.arange(prob["n_cameras"]) // -(-prob["n_cameras"] // S)
     n_a = 9 * np.bincount(cam_part, minlength=S)
-    npad = 64 * ((n_a + 63) // 64)
-    flops = float(2.0 * np.sum(npad.astype(np.float64) ** 3) / 3.0)  # Cholesky: n^3/3 multiply-adds
+    flops = float(2.0 * np.sum(n_a.astype(np.float64) ** 3) / 3.0)  # Cholesky: n^3/3 multiply-adds
     fact_ms = groups["cholesky"] / max(groups["lm_attempts"], 1)
+    solve_ms = groups["solve"] / max(groups["lm_attempts"], 1)
     achieved = flops / (fact_ms / 1e3) / 1e12
     out = {
         "metric": "observation-iterations/s, device surrogate (exact intra-partition pairs, LM per partition)",
@@ -282,7 +284,9 @@ def bench_partition(args, prob, S):
         "roofline": {"bound": "alu", "kernel": "Cholesky of the reduced camera systems (kp_chol_*)",
                      "achieved": achieved, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_TFLOPS, "traffic": None,
-                     "algorithmic_flops_per_factorisation": flops, "avg_factorisation_ms": fact_ms},
+                     "algorithmic_flops_per_factorisation": flops, "avg_factorisation_ms": fact_ms,
+                     "order_per_partition": int(n_a.max()),
+                     "factorisation_plus_solve_ms_per_attempt": fact_ms + solve_ms},
         "group_ms_per_step": {k: v / steps for k, v in groups.items() if k not in ("lm_attempts", "cholesky_launches")},
         "lm_attempts_per_step": groups["lm_attempts"] / steps,
         "setup_s": setup_s,
@@ -433,7 +437,10 @@ def main():
         eq = equal_objective(prob, ms_per_step, ms32, cfg["iterations"] or 200, S, make)
         out["fp32_mixed"] = {"value": K / (ms32 / 1e3), "ms_per_step": ms32, "ms_per_step_repeats": reps32,
                              "kernels": {n: {"ms": float(k32[i]),
-                                             "GBs": kb32[n] / (k32[i] / 1e3) / 1e9 if n in kb32 else None}
+                                             "algorithmic_bytes": kb32.get(n),
+                                             "GBs": kb32[n] / (k32[i] / 1e3) / 1e9 if n in kb32 else None,
+                                             "traffic": (measured_traffic(n, args.workload, "fp32_mixed")
+                                                         if n in kb32 else None)}
                                          for i, n in enumerate(names)},
                              "equal_objective": eq}
     if args.copy_calibration:
