@@ -1068,17 +1068,24 @@ __global__ __launch_bounds__(256) void kp_chol_trsm(PP p, int k) {
     }
 }
 
-// Step k: A_ij -= L_ik L_jk^T for tiles k < j <= i; the inner dimension in
-// two halves of 32 columns (34 KB of LDS).  The block of tile (k+1, k+1),
-// whose update is the last one it receives, completes it in LDS and
-// factors it for step k + 1 while the other tiles update.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+// Step k: A_ij -= L_ik L_jk^T for tiles k < j <= i, on the matrix cores:
+// v_mfma_f64_16x16x4f64, each wave a 32 x 32 quadrant of the tile as 2 x 2
+// blocks of 16 x 16, the inner dimension in two halves of 32 columns staged
+// in LDS (rows padded to 34 doubles: two-way bank conflicts for the operand
+// reads).  Operand layout of the instruction: lane l holds A(l mod 16,
+// l / 16) and B(l / 16, l mod 16); accumulator register v of lane l holds
+// D(l / 16 + 4 v, l mod 16).  The block of tile (k+1, k+1), whose update is
+// the last one it receives, completes it in LDS and factors it for step
+// k + 1 while the other tiles update.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kp_chol_update(PP p, int k) {
-    constexpr int kH = kNB / 2;
-    __shared__ __align__(16) double sh[2 * kNB * (kH + 1)];
+    constexpr int kH = kNB / 2, kS = kH + 2;
+    __shared__ __align__(16) double sh[2 * kNB * kS];
     __shared__ __align__(16) double ybuf[2 * kNB];
-    static_assert(kNB * kLD <= 2 * kNB * (kH + 1), "tile buffer");
-    double (*Li)[kH + 1] = reinterpret_cast<double (*)[kH + 1]>(sh);
-    double (*Lj)[kH + 1] = reinterpret_cast<double (*)[kH + 1]>(sh + kNB * (kH + 1));
+    static_assert(kNB * kLD <= 2 * kNB * kS, "tile buffer");
+    double (*Li)[kS] = reinterpret_cast<double (*)[kS]>(sh);
+    double (*Lj)[kS] = reinterpret_cast<double (*)[kS]>(sh + kNB * kS);
     const int a = blockIdx.y;
     if (p.ps[(size_t)a * kPS + P_ACTIVE] == 0.0) return;
     const int m = p.nt[a] - k - 1;  // trailing tiles
@@ -1091,16 +1098,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int i = k + 1 + ii, j = k + 1 + jj;
     const int np = p.npad[a];
     const double* base = p.Smat + p.soff[a];
-    const int tid = threadIdx.x;
-    const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
+    const int tid = threadIdx.x, l = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rb = 32 * (w >> 1), cb = 32 * (w & 1);  // the wave's quadrant
+    const int lr = l & 15, lk = l >> 4;
     double* Aij = p.Smat + p.soff[a] + (size_t)(kNB * i) * np + kNB * j;
     // tile (k+1, k+1) is factored after its update: its b entry now
-    const double bv = t == 0 ? p.vec[p.voff[a] + kNB * (k + 1) + (tid & 63)] : 0.0;
-    double acc[4][4];
+    const double bv = t == 0 ? p.vec[p.voff[a] + kNB * (k + 1) + l] : 0.0;
+    mfma_d4 acc[2][2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int v = 0; v < 2; ++v) acc[u][v] = mfma_d4{0.0, 0.0, 0.0, 0.0};
     for (int h = 0; h < kNB; h += kH) {
         __syncthreads();
         double vi[kNB * kH / 256], vj[kNB * kH / 256];
@@ -1117,33 +1126,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             Lj[r][c] = vj[u];
         }
         __syncthreads();
-        for (int kk = 0; kk < kH; ++kk) {
-            double x[4], y[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = Li[r0 + u][kk];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) y[v] = Lj[c0 + v][kk];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
+        for (int ks = 0; ks < kH; ks += 4) {
+            const double a0 = Li[rb + lr][ks + lk], a1 = Li[rb + 16 + lr][ks + lk];
+            const double b0 = Lj[cb + lr][ks + lk], b1 = Lj[cb + 16 + lr][ks + lk];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
     if (t == 0) {  // tile (k+1, k+1): complete it in LDS and factor it
         double (*T)[kLD] = reinterpret_cast<double (*)[kLD]>(sh);
         __syncthreads();  // every wave is done with Li and Lj
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) T[r0 + u][c0 + v] = Aij[(size_t)(r0 + u) * np + c0 + v] - acc[u][v];
+            for (int v = 0; v < 2; ++v)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = rb + 16 * u + lk + 4 * q, c = cb + 16 * v + lr;
+                    T[r][c] = Aij[(size_t)r * np + c] - acc[u][v][q];
+                }
         __syncthreads();
         factor_tile(p, a, k + 1, T, ybuf, bv);
         return;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Aij[(size_t)(r0 + u) * np + c0 + v] -= acc[u][v];
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = rb + 16 * u + lk + 4 * q, c = cb + 16 * v + lr;
+                Aij[(size_t)r * np + c] -= acc[u][v][q];
+            }
 }
 
 // Stages the strictly lower part of diagonal tile c0 / 64 in D (LDS, only
