@@ -279,9 +279,12 @@ void carve(const Layout& L, bool fp32, Carver& c, Params& p) {
     p.uv32 = fp32 ? c.take<float2>(K) : nullptr;
     p.obs_lm = c.take<unsigned>(K);
     p.obs_orig = c.take<int>(K);
-    p.luv = c.take<double2>(K);
-    p.luv32 = fp32 ? c.take<float2>(K) : nullptr;
-    p.slot_cam = c.take<unsigned>(K);
+    // at least one slot, so that the landmark pass may read a slot it
+    // discards even when nothing is observed
+    const int64_t K1 = std::max<int64_t>(K, 1);
+    p.luv = c.take<double2>(K1);
+    p.luv32 = fp32 ? c.take<float2>(K1) : nullptr;
+    p.slot_cam = c.take<unsigned>(K1);
     p.slot_obs = c.take<int>(K);
     p.tile_cam = c.take<int>(T);
     p.tile_begin = c.take<int>(T);

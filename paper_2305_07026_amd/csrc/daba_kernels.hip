@@ -124,6 +124,17 @@ __device__ __forceinline__ LmRead<float> read_pair(const float* __restrict__ bas
     return o;
 }
 
+// A 64-byte FP64 pair record from LDS.
+__device__ __forceinline__ LmRead<double> lds_pair(const char* rec) {
+    const double2* q = reinterpret_cast<const double2*>(rec);
+    const double2 a = q[0], b = q[1], c = q[2], d = q[3];
+    LmRead<double> o;
+    o.lk[0] = a.x; o.lk[1] = a.y; o.lk[2] = b.x;
+    o.beta = (int)__double_as_longlong(b.y);
+    o.lp[0] = c.x; o.lp[1] = c.y; o.lp[2] = d.x;
+    return o;
+}
+
 // candidate pair records read by iteration k (written by iteration k - 1)
 template <typename R>
 __device__ __forceinline__ const R* pair_base(const Params& p, int k, int cand);
@@ -813,18 +824,68 @@ __device__ __forceinline__ void wait_lds() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Candidate pair record (l^(k+1) candidate, partition id, l^k) of iteration k.
-__device__ __forceinline__ void write_cand_pair(const Params& p, int k, int cand, int li, const double* ln,
-                                                double beta_bits, const double* lk) {
-    double2* q = reinterpret_cast<double2*>(p.lcp[k & 1][cand] + (size_t)li * kLmPair);
-    q[0] = make_double2(ln[0], ln[1]);
-    q[1] = make_double2(ln[2], beta_bits);
-    q[2] = make_double2(lk[0], lk[1]);
-    q[3] = make_double2(lk[2], 0.0);
-    if (p.fp32) {
-        float4* f = reinterpret_cast<float4*>(p.lcp32[k & 1][cand] + (size_t)li * kLmPair);
-        f[0] = make_float4((float)ln[0], (float)ln[1], (float)ln[2], __int_as_float((int)__double_as_longlong(beta_bits)));
-        f[1] = make_float4((float)lk[0], (float)lk[1], (float)lk[2], 0.0f);
+// The candidate pair records (the candidate l^(k+1), the partition id, l^k)
+// of a landmark group (n <= 64 consecutive landmarks from lm0) written by
+// iteration k, stored cooperatively: each lane's records go to LDS,
+// then every store instruction writes 1 KB of consecutive bytes, 16 per
+// lane, in whole lines, instead of each lane's own record in strided 16-byte
+// pieces (those partial-line stores took about a quarter of the landmark
+// pass at 60M observations).  The LDS (at least 8 KB) is free: the group's
+// last step has read its camera records.  A wave's LDS operations complete
+// in program order, so a later staging write cannot overtake an earlier
+// read.  Lanes past n stage lane 0's landmark and store nothing.
+template <bool ACC>
+__device__ __forceinline__ void store_group_pairs(const Params& p, int k, int lm0, int n, char* lds,
+                                                  const double* lm, const double* la, double beta_bits,
+                                                  const double* lk) {
+    const int lane = threadIdx.x;
+    constexpr int kC = ACC ? 2 : 1;
+    {
+        double2* s0 = reinterpret_cast<double2*>(lds + 64 * lane);
+        s0[0] = make_double2(lm[0], lm[1]);
+        s0[1] = make_double2(lm[2], beta_bits);
+        s0[2] = make_double2(lk[0], lk[1]);
+        s0[3] = make_double2(lk[2], 0.0);
+        if constexpr (ACC) {
+            double2* s1 = reinterpret_cast<double2*>(lds + 4096 + 64 * lane);
+            s1[0] = make_double2(la[0], la[1]);
+            s1[1] = make_double2(la[2], beta_bits);
+            s1[2] = make_double2(lk[0], lk[1]);
+            s1[3] = make_double2(lk[2], 0.0);
+        }
+    }
+    const int bytes = 64 * n;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) {
+        char* dst = reinterpret_cast<char*>(p.lcp[k & 1][c] + (size_t)lm0 * kLmPair);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int off = 1024 * i + 16 * lane;
+            const float4 v = *reinterpret_cast<const float4*>(lds + 4096 * c + off);
+            if (off < bytes) *reinterpret_cast<float4*>(dst + off) = v;
+        }
+    }
+    if (p.fp32) {  // the 32-byte FP32 copies, staged over the first 4 KB
+        const float bf = __int_as_float((int)__double_as_longlong(beta_bits));
+        float4* s0 = reinterpret_cast<float4*>(lds + 32 * lane);
+        s0[0] = make_float4((float)lm[0], (float)lm[1], (float)lm[2], bf);
+        s0[1] = make_float4((float)lk[0], (float)lk[1], (float)lk[2], 0.0f);
+        if constexpr (ACC) {
+            float4* s1 = reinterpret_cast<float4*>(lds + 2048 + 32 * lane);
+            s1[0] = make_float4((float)la[0], (float)la[1], (float)la[2], bf);
+            s1[1] = make_float4((float)lk[0], (float)lk[1], (float)lk[2], 0.0f);
+        }
+        const int bytes32 = 32 * n;
+#pragma unroll
+        for (int c = 0; c < kC; ++c) {
+            char* dst = reinterpret_cast<char*>(p.lcp32[k & 1][c] + (size_t)lm0 * kLmPair);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int off = 1024 * i + 16 * lane;
+                const float4 v = *reinterpret_cast<const float4*>(lds + 2048 * c + off);
+                if (off < bytes32) *reinterpret_cast<float4*>(dst + off) = v;
+            }
+        }
     }
 }
 
@@ -865,9 +926,34 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
         const int n = uniform_int(p.group_n[g]), D = uniform_int(p.group_deg[g]);
         const bool on = lane < n;
         const int ln = on ? lane : 0;  // lanes past n read lane 0's data and discard it
-        const int li = uniform_int(p.group_lm0[g]) + ln;
+        const int li0 = uniform_int(p.group_lm0[g]);
         const int64_t base = p.group_base[g] + ln;
-        const LmRead<double> L = read_pair(lpb, li);
+        // slot q of the lane's landmark, clamped to the group's last slot and
+        // to the slot arrays (which hold at least one slot), so that every
+        // group issues the same loads, also one with no observations
+        const int64_t slot_max = p.K > 0 ? p.K - 1 : 0;
+        auto slot_at = [&](int q) { return min(base + (int64_t)min(q, max(D - 1, 0)) * n, slot_max); };
+        // the first two slots' addresses before any DMA is in flight (the
+        // compiler would wait for every outstanding DMA before using a value
+        // loaded earlier)
+        const int64_t sl0 = slot_at(0), sl1 = slot_at(1);
+        __builtin_amdgcn_sched_barrier(0);
+        // the group's pair records (consecutive landmarks) arrive in LDS as
+        // 1 KB runs, 16 bytes per lane, rather than as each lane's own record
+        // in strided pieces; lanes past the group's records re-read its last
+        // 16 bytes into slots nobody reads
+        {
+            const char* src = reinterpret_cast<const char*>(lpb + (size_t)li0 * kLmPair);
+            const int last = 64 * n - 16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dma16(src + min(1024 * i + 16 * lane, last), lds + 1024 * i);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        SlotObs<R> s0 = read_slot<R>(p, sl0);
+        SlotObs<R> s1 = read_slot<R>(p, sl1);
+        wait_vmem_n<4>();  // the pair records; slots 0 and 1 stay in flight
+        const LmRead<double> L = lds_pair(lds + 64 * ln);
+        wait_lds();  // the record is in registers before the cameras' DMA reuses the LDS
         // the evaluation points in the evaluation type (as the camera tiles
         // form them from the pair records)
         const R lk0 = (R)L.lk[0], lk1 = (R)L.lk[1], lk2 = (R)L.lk[2];
@@ -882,14 +968,11 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
         // q - 1); the prefetch past the last slot re-reads it, so that every
         // step issues the same loads and the compiler's wait counts stay
         // exact.
-        auto slot_at = [&](int q) { return base + (int64_t)min(q, D - 1) * n; };
         auto rec_of = [&](unsigned cam) {
             // the record of the candidate the camera's partition chose
             return (unsigned)chosen(restart, (int)(cam >> kCamBits)) * M + (cam & kCamMask);
         };
         if (D > 0) {
-            SlotObs<R> s0 = read_slot<R>(p, slot_at(0));
-            SlotObs<R> s1 = read_slot<R>(p, slot_at(1));
             R ux = s0.ux, uy = s0.uy;
             dma_cams<kSets>(ckb, cbb, rec_of(on ? s0.cam : 0u), lds);
             __builtin_amdgcn_sched_barrier(0);
@@ -916,8 +999,9 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
                 wait_vmem_n<2>();  // step q + 1's records; slot q + 3 stays in flight
             }
         }
-        if (!on) continue;
-        // closed forms: l = l^y + V / (2W + xi) about each linearization point
+        // closed forms: l = l^y + V / (2W + xi) about each linearization
+        // point (every lane: a lane past n repeats lane 0's landmark, counts
+        // nothing and stores nothing)
         double dl[3], nm = 0.0, dv = 0.0;
         const double den0 = 2.0 * W0 + xi;
 #pragma unroll
@@ -926,13 +1010,13 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
             nm += dl[a] * dl[a];
             dv += dl[a] * V0[a];
         }
-        dmm += (W0 + 0.5 * xi) * nm - dv;
+        if (on) dmm += (W0 + 0.5 * xi) * nm - dv;
         const double beta_bits = __longlong_as_double((long long)L.beta);
         const double lm[3] = {L.lk[0] + dl[0], L.lk[1] + dl[1], L.lk[2] + dl[2]};
-        write_cand_pair(p, k, 0, li, lm, beta_bits, L.lk);
+        double la[3] = {lm[0], lm[1], lm[2]};
         if constexpr (ACC) {
             const double den1 = 2.0 * W1 + xi;
-            double la[3], na = 0.0, va = 0.0;
+            double na = 0.0, va = 0.0;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double lbar = L.lk[a] + gam * (L.lk[a] - L.lp[a]);
@@ -942,9 +1026,9 @@ __device__ __forceinline__ void lm_role(const Params& p, int k, int lb, char* ld
                 va += da * V0[a];
             }
             // the accelerated candidate measured on the surrogate about x^k
-            dacc += (W0 + 0.5 * xi) * na - va;
-            write_cand_pair(p, k, 1, li, la, beta_bits, L.lk);
+            if (on) dacc += (W0 + 0.5 * xi) * na - va;
         }
+        store_group_pairs<ACC>(p, k, li0, n, lds, lm, la, beta_bits, L.lk);
     }
     dmm = wave_sum(dmm);
     dacc = wave_sum(dacc);
