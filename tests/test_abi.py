@@ -168,3 +168,26 @@ def test_part_rejects_a_partition_beyond_the_camera_limit():
     assert b"at most" in B.lib.daba_part_last_error(None)
     keep, pr, opt = _part_args(big, n_partitions=2)  # 1,050 cameras each: accepted
     assert B.lib.daba_part_workspace_bytes(C.byref(pr), C.byref(opt)) > 0
+
+
+def test_size_limits_on_host():
+    """The largest problem the packed observation words allow (cameras below
+    2^24, landmarks below 2^26, 64 partitions) is sized; one more camera or
+    landmark is rejected before anything is read, and so is a partition
+    count above 64.  No observations, so that the limits stay cheap."""
+    P = C.POINTER
+    cams = np.tile(np.r_[np.eye(3).ravel(), 0.0, 0.0, 10.0, 500.0, 0.0, 0.0], (1, 1))
+    lms = np.zeros((1, 3))
+    empty_i, empty_d = np.zeros(1, np.int32), np.zeros(2)
+
+    def sized(M, N, S):
+        st = B.DabaProblem(M, N, 0, empty_i.ctypes.data_as(P(C.c_int32)), empty_i.ctypes.data_as(P(C.c_int32)),
+                           empty_d.ctypes.data_as(P(C.c_double)), cams.ctypes.data_as(P(C.c_double)),
+                           lms.ctypes.data_as(P(C.c_double)), S, None, None, 512.0)
+        return B.lib.daba_workspace_bytes(C.byref(st), C.byref(_opts()))
+
+    assert sized((1 << 24) - 1, 1, 64) > 0
+    assert sized(1 << 24, 1, 64) == 0
+    assert sized(1, 1 << 26, 1) == 0
+    assert sized(1, 1, 65) == 0
+    assert sized(1, 1, 0) == 0
