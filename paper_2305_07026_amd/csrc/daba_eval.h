@@ -46,6 +46,67 @@ __device__ __forceinline__ R loss_rho(R s, R delta, R& w) {
     }
 }
 
+// 1/x for a positive normal x, without the IEEE division sequence (its
+// range scaling and fix-up are not needed for the squared distances of an
+// observation): in FP32 the hardware reciprocal (about 1 ulp); in FP64 the
+// hardware estimate refined by two Newton steps y <- y + y (1 - x y), each
+// of which squares the relative error, to a few ulp.
+template <typename R>
+__device__ __forceinline__ R recip(R x);
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+// sqrt(s) and 1/sqrt(s) together for a positive normal s.  FP32: the
+// hardware reciprocal square root (about 1 ulp).  FP64: from the hardware
+// estimate y, g = s y -> sqrt(s) and h = y / 2 -> 1 / (2 sqrt(s)) refined
+// together by two coupled Newton steps on the residual 1/2 - g h.
+template <typename R>
+__device__ __forceinline__ void sqrt_rsqrt(R s, R& rs, R& irs);
+template <>
+__device__ __forceinline__ void sqrt_rsqrt<float>(float s, float& rs, float& irs) {
+    irs = __builtin_amdgcn_rsqf(s);
+    rs = s * irs;
+}
+template <>
+__device__ __forceinline__ void sqrt_rsqrt<double>(double s, double& rs, double& irs) {
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    e = fma(-g, h, 0.5);
+    rs = fma(g, e, g);
+    irs = 2.0 * fma(h, e, h);
+}
+
+// The loss of loss_rho for the iteration's per-observation passes, with the
+// Huber branch's square root and division taken by sqrt_rsqrt.
+template <int LOSS, typename R>
+__device__ __forceinline__ R loss_rho_iter(R s, R delta, R& w) {
+    if constexpr (LOSS == 1) {
+        if (s <= delta * delta) {
+            w = (R)1;
+            return s;
+        }
+        R rs, irs;
+        sqrt_rsqrt<R>(s, rs, irs);
+        w = delta * irs;
+        return (R)2 * delta * rs - delta * delta;
+    } else {
+        return loss_rho<LOSS, R>(s, delta, w);
+    }
+}
+
 // One observation at camera c and landmark l (Sec. III): the rotated ray Rp,
 // m = l - t, the depth scalar lambda (eq. lambdaij), the world-frame residual
 // e_w = R p - lambda m (= R e of eq. error), |e|^2, the weight w = rho' and rho.
@@ -64,12 +125,12 @@ __device__ __forceinline__ void eval_obs(const CamT<R>& c, R l0, R l1, R l2, R u
     o.m[1] = l1 - c.t[1];
     o.m[2] = l2 - c.t[2];
     o.r2 = o.m[0] * o.m[0] + o.m[1] * o.m[1] + o.m[2] * o.m[2];
-    R inv = (R)1 / o.r2;
+    const R inv = recip<R>(o.r2);
     o.lam = (o.m[0] * o.Rp[0] + o.m[1] * o.Rp[1] + o.m[2] * o.Rp[2]) * inv;
 #pragma unroll
     for (int a = 0; a < 3; ++a) o.e[a] = o.Rp[a] - o.lam * o.m[a];
     o.s = o.e[0] * o.e[0] + o.e[1] * o.e[1] + o.e[2] * o.e[2];
-    o.rho = loss_rho<LOSS, R>(o.s, delta, o.w);
+    o.rho = loss_rho_iter<LOSS, R>(o.s, delta, o.w);
 }
 
 // eq. error written out in the camera frame for any 3x3 R (the form the

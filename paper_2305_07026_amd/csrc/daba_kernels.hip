@@ -147,10 +147,71 @@ __device__ __forceinline__ const float* pair_base<float>(const Params& p, int k,
     return p.lcp32[(k + 1) & 1][cand];
 }
 
-// Segmented sum over lanes whose keys are sorted (equal keys contiguous);
-// the last lane of each run adds the run's sum into bins[key].
+// v plus the value that DPP control CTRL moves into this lane, or plus zero
+// where the lane has no source or its row is masked off (a 64-bit value moves
+// as its two 32-bit halves from the same source lane).  With every row
+// enabled a lane without a source reads zero (bound_ctrl), so the move needs
+// no zeroed destination.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+    const long long b = __double_as_longlong(v);
+    int lo, hi;
+    if constexpr (ROW_MASK == 0xf) {
+        lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    }
+    return v + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active):
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes (a Hillis-Steele
+// scan), then lane 15's row total into rows 1 and 3 and lane 31's into rows
+// 2 and 3.  Cross-lane moves by DPP, with no LDS round trip.
+__device__ __forceinline__ double wave_scan(double v) {
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31
+    return v;
+}
+
+// Segmented sum over the lanes of a wave (every lane active) whose keys are
+// sorted (equal keys contiguous; key < 0 adds nothing): with P the inclusive
+// prefix sum, a run [a, b] of key k sums to P[b] - P[a - 1], so the last lane
+// of each run adds P to bins[key], then subtracts it from the bins of the next
+// run's key.  Within each of the two updates the lanes name distinct bins, and
+// a wave's LDS operations complete in order.
 __device__ __forceinline__ void bin_add_sorted(double v0, double v1, int key, int lane, double* bins0,
                                                double* bins1) {
+    const double P0 = wave_scan(v0), P1 = wave_scan(v1);
+    // the shuffle with every lane active (an inactive source lane reads as 0)
+    int nk = __shfl_down(key, 1, kWave);
+    if (lane == kWave - 1) nk = -1;
+    if (nk != key) {
+        if (key >= 0) {
+            bins0[key] += P0;
+            bins1[key] += P1;
+        }
+        // another lane's bin: the compiler must not move these reads above
+        // the writes (it may assume key != nk in this thread)
+        asm volatile("" ::: "memory");
+        if (nk >= 0) {
+            bins0[nk] -= P0;
+            bins1[nk] -= P1;
+        }
+    }
+}
+
+// The same segmented sum through LDS permutes (fewer VALU instructions, more
+// LDS traffic): a segmented Hillis-Steele scan, the last lane of each run
+// adding the run's sum into bins[key].
+__device__ __forceinline__ void bin_add_sorted_lds(double v0, double v1, int key, int lane, double* bins0,
+                                                   double* bins1) {
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
         double o0 = __shfl_up(v0, d, kWave);
@@ -169,17 +230,13 @@ __device__ __forceinline__ void bin_add_sorted(double v0, double v1, int key, in
     }
 }
 
-// Adds a run's per-lane sums into bins[key] (no-op for key < 0) and clears them.
-__device__ __forceinline__ void flush_run(int key, double& r0, double& r1, int lane, double* bins0, double* bins1) {
-    if (key >= 0) {
-        const double s0 = wave_sum(r0), s1 = wave_sum(r1);
-        if (lane == 0) {
-            bins0[key] += s0;
-            bins1[key] += s1;
-        }
-    }
-    r0 = 0.0;
-    r1 = 0.0;
+// The observation pass's segmented sum, each form where it is the faster
+// one (measured): FP64, whose LDS also serves the 64-byte pair records, bins
+// by DPP; FP32, whose VALU is the busier unit, through LDS permutes.
+template <typename R>
+__device__ __forceinline__ void bin_runs(double v0, double v1, int key, int lane, double* bins0, double* bins1) {
+    if constexpr (sizeof(R) == 8) bin_add_sorted(v0, v1, key, lane, bins0, bins1);
+    else bin_add_sorted_lds(v0, v1, key, lane, bins0, bins1);
 }
 
 // --------------------------------------------------- restart test (Sec. V)
@@ -472,7 +529,7 @@ __device__ __forceinline__ void tile_role(const Params& p, int k, int t, const T
     const char* __restrict__ pbase = reinterpret_cast<const char*>(pair_base<R>(p, k, 0));
     const uint64_t cand_stride = (uint64_t)p.N * kRecB;
     bool bad = false;
-    int run_key = -1;
+    int run_key = -1;  // this lane's current run: key and sums
     double run0 = 0.0, run1 = 0.0;
     __syncthreads();
 
@@ -641,26 +698,23 @@ __device__ __forceinline__ void tile_role(const Params& p, int k, int t, const T
                 add_moments<R>(acc + kMom, eb.w, eb.lam, ux, uy, r2u, r4u, r6u, r8u, eb.e);
             }
         }
-        {
-            // landmark-side shares by landmark partition.  Within a camera the
-            // observations are sorted by landmark partition, so most steps
-            // hold one partition: accumulate those per lane and reduce once
-            // per run; a step that straddles partitions uses a segmented sum.
-            const int k0 = uniform_int(key);
-            const bool uni = __all(!on || key == k0);
-            if (uni) {
-                if (k0 != run_key) {
-                    flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
-                    run_key = k0;
-                }
-                run0 += hF;
-                run1 -= gp;
-            } else {
-                flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
-                run_key = -1;
-                bin_add_sorted(hF, -gp, key, lane, bins[0], bins[1]);
+        // landmark-side shares by landmark partition.  Within a camera the
+        // observations are sorted by landmark partition, so the lanes' keys
+        // are sorted within a step and each lane's keys never decrease from
+        // step to step.  Each lane sums its own run of one key; when any
+        // lane's key changes, the finished runs (keyed by the lanes' previous
+        // keys, sorted too) are binned by one segmented sum.
+        if (__any(key != run_key)) {
+            const bool done = key != run_key;
+            bin_runs<R>(done ? run0 : 0.0, done ? run1 : 0.0, run_key, lane, bins[0], bins[1]);
+            if (done) {
+                run0 = 0.0;
+                run1 = 0.0;
+                run_key = key;
             }
         }
+        run0 += hF;
+        run1 -= gp;
     };
 
     if (ns > 0) {
@@ -680,7 +734,7 @@ __device__ __forceinline__ void tile_role(const Params& p, int k, int t, const T
         if (st + 1 < ns) step(st + 1, B, A, li0, li1);
         if (st + 2 < ns) step(st + 2, C, B, li1, li2);
     }
-    flush_run(run_key, run0, run1, lane, bins[0], bins[1]);
+    bin_runs<R>(run0, run1, run_key, lane, bins[0], bins[1]);
     if (bad) p.st[0].err = -5;
 
     // tile totals: LDS transpose in the two buffers (rows 0..6 in A, 7..13
